@@ -1,0 +1,80 @@
+"""Pins for the float64 schedule-model reference (no GPU).
+
+Gradients are checked by central finite differences (not by retyping the chain
+rule); Adam by its closed-form first step and by convergence on a quadratic.
+"""
+import numpy as np
+
+from oracle import mlp
+
+
+def make_batch(seed, n=16, nin=4, nout=6):
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((n, nin))
+    T = rng.standard_normal((n, nout))
+    M = (rng.random((n, nout)) < 0.8).astype(np.float64)
+    return X, T, M
+
+
+def test_gradients_match_central_finite_differences():
+    sizes = [4, 7, 5, 6, 6]
+    params = mlp.init_params(sizes, seed=3)
+    for i in range(1, len(params), 2):       # non-zero biases so no unit sits exactly at the ReLU kink
+        params[i] = np.random.default_rng(i).standard_normal(params[i].shape) * 0.1
+    X, T, M = make_batch(1, nout=6)
+    Y, cache = mlp.forward(params, X)
+    grads = mlp.backward(params, cache, Y, T, M)
+    h = 1e-6
+    rng = np.random.default_rng(0)
+    for pi, p in enumerate(params):
+        flat = p.reshape(-1)
+        for idx in rng.choice(flat.size, size=min(flat.size, 12), replace=False):
+            old = flat[idx]
+            flat[idx] = old + h
+            lp = mlp.loss(mlp.forward(params, X)[0], T, M)
+            flat[idx] = old - h
+            lm = mlp.loss(mlp.forward(params, X)[0], T, M)
+            flat[idx] = old
+            fd = (lp - lm) / (2 * h)
+            an = grads[pi].reshape(-1)[idx]
+            assert abs(fd - an) <= 1e-6 + 1e-5 * abs(fd), (pi, idx, fd, an)
+
+
+def test_output_bias_gradient_closed_form_with_zero_weights():
+    sizes = [4, 8, 8, 3]
+    params = [np.zeros_like(p) for p in mlp.init_params(sizes)]
+    params[-1] = np.array([0.5, -1.0, 2.0])
+    X, T, M = make_batch(2, nout=3)
+    Y, cache = mlp.forward(params, X)
+    assert np.allclose(Y, params[-1])
+    g = mlp.backward(params, cache, Y, T, M)
+    expect = 2 * ((params[-1] - T) * M).sum(axis=0) / M.sum()
+    assert np.allclose(g[-1], expect)
+    assert all(np.all(gi == 0) for gi in g[:-2])   # dead ReLUs pass no gradient further down
+
+
+def test_adam_first_step_is_lr_times_sign():
+    p = [np.array([1.0, -2.0, 3.0])]
+    g = [np.array([0.3, -5.0, 1e-3])]
+    z = [np.zeros(3)]
+    newp, _, _ = mlp.adam_step(p, g, z, z, t=1, lr=0.01, eps=1e-12)
+    assert np.allclose(newp[0], p[0] - 0.01 * np.sign(g[0]))
+
+
+def test_adam_minimises_a_quadratic_and_training_reduces_loss():
+    p = [np.array([5.0, -3.0])]
+    m = [np.zeros(2)]
+    v = [np.zeros(2)]
+    for t in range(1, 3001):
+        p, m, v = mlp.adam_step(p, [2 * p[0]], m, v, t, lr=0.05)
+    assert np.all(np.abs(p[0]) < 1e-2)
+    sizes = [4, 16, 16, 3]
+    params = mlp.init_params(sizes, seed=1)
+    X, T, M = make_batch(3, n=64, nout=3)
+    mo = [np.zeros_like(q) for q in params]
+    vo = [np.zeros_like(q) for q in params]
+    l0 = mlp.loss(mlp.forward(params, X)[0], T, M)
+    for t in range(1, 301):
+        Y, c = mlp.forward(params, X)
+        params, mo, vo = mlp.adam_step(params, mlp.backward(params, c, Y, T, M), mo, vo, t, lr=1e-2)
+    assert mlp.loss(mlp.forward(params, X)[0], T, M) < 0.5 * l0
