@@ -1,0 +1,116 @@
+/*
+ * gf2.h -- dense matrix multiplication over GF(2) on AMD MI355X (gfx950).
+ *
+ * The operation (Sections 1 and 2.3 of Albrecht, Bard and Hart, "Efficient
+ * Multiplication of Dense Matrices over GF(2)"): for A (m x k) and B (k x n)
+ * over the field with two elements, where addition is XOR and multiplication
+ * is AND,
+ *
+ *     C[i][j] = XOR over t < k of (A[i][t] AND B[t][j]).
+ *
+ * It is computed by Strassen-Winograd recursion (Section 4, Algorithm 4) over a
+ * Method of the Four Russians base case (Section 3, Algorithms 1-3), or over an
+ * exact int8 matrix-core base case, or a popcount base case, chosen per call.
+ * Every schedule gives the same bits: the result is unique and exact.
+ *
+ * LAYOUT (Section 2.1, "flat row-major"): a matrix with `rows` rows and `cols`
+ * columns is `rows` rows of `ld` 64-bit words, ld >= ceil(cols/64).  Column j
+ * of a row is bit (j & 63) of word (j >> 6) (least significant bit first).
+ *   - Bits at columns >= cols in a row's last word are padding.  Inputs'
+ *     padding is ignored.  gf2_mul writes C's padding as 0; gf2_addmul leaves
+ *     it unchanged.
+ *   - Words ceil(cols/64) .. ld-1 of a row (the stride gap) are never read
+ *     or written.
+ *   - Dimensions are in entries (bits); ld is in words.
+ *
+ * MEMORY AND OWNERSHIP.  A, B and C are device pointers (8-byte aligned) owned
+ * by the caller, on the current HIP device.  C must not overlap A or B.  The
+ * library owns a per-device workspace (Strassen temporaries, split-K partials,
+ * descriptor staging), cached schedules and the schedule model; gf2_shutdown()
+ * releases them.
+ *
+ * STREAMS.  `stream` is a hipStream_t (NULL = the null stream).  Calls enqueue
+ * work and return without waiting, like BLAS; buffers must stay valid until the
+ * stream reaches the work.  Workspace use is ordered across streams with events.
+ *
+ * ERRORS.  Arguments are validated before anything is enqueued; on error
+ * nothing is enqueued and C is untouched.  A failed launch returns
+ * GF2_ERR_DEVICE; gf2_last_error() gives the text (thread-local).  Faults in
+ * kernels surface at the caller's next synchronisation.
+ */
+#ifndef GF2_H
+#define GF2_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum gf2_status {
+  GF2_OK = 0,
+  GF2_ERR_INVALID_ARG = 1, /* negative size, short ld, null or misaligned pointer, bad schedule */
+  GF2_ERR_ALIAS = 2,       /* C overlaps A or B (or two C's of a batch overlap) */
+  GF2_ERR_ALLOC = 3,       /* device or host allocation failed */
+  GF2_ERR_CAPTURE = 4,     /* would allocate while the stream is being captured */
+  GF2_ERR_DEVICE = 5,      /* a HIP call or launch failed */
+  GF2_ERR_UNSUPPORTED = 6  /* shape or option outside what the kernels handle */
+} gf2_status;
+
+/* Base-case kernels. */
+enum {
+  GF2_KERNEL_AUTO = 0,  /* library chooses */
+  GF2_KERNEL_M4RM = 1,  /* Four Russians, Gray-code tables in LDS (Section 3) */
+  GF2_KERNEL_MFMA = 2,  /* 0/1 int8 matrix-core product, low bit of the int32 sum */
+  GF2_KERNEL_CUBIC = 3  /* AND + popcount parity against B transposed (Section 2.3) */
+};
+
+/* A schedule: which base kernel, its tile variant, the Strassen-Winograd
+ * crossover and the number of k slices.  Zero fields mean "default". */
+typedef struct gf2_schedule {
+  int32_t kernel;   /* GF2_KERNEL_* */
+  int32_t variant;  /* kernel tile variant (see gf2_kernel_variants) */
+  int32_t cutoff;   /* recurse while min(m, k, n) > cutoff; 0 = no recursion (Section 5, c_o) */
+  int32_t splitk;   /* k split into this many slices XOR-combined into C; 0 or 1 = none */
+} gf2_schedule;
+
+/* C := A*B.  Section 1 / Section 2.3 definition above.  m, k, n >= 0.
+ * k = 0 sets C's valid bits to 0; m = 0 or n = 0 does nothing. */
+gf2_status gf2_mul(uint64_t* C, int64_t ldc, const uint64_t* A, int64_t lda, const uint64_t* B, int64_t ldb,
+                   int64_t m, int64_t k, int64_t n, void* stream);
+
+/* C := C + A*B (XOR-accumulate).  Same arguments as gf2_mul; k = 0 does nothing. */
+gf2_status gf2_addmul(uint64_t* C, int64_t ldc, const uint64_t* A, int64_t lda, const uint64_t* B,
+                      int64_t ldb, int64_t m, int64_t k, int64_t n, void* stream);
+
+/* gf2_mul / gf2_addmul (accumulate != 0) with an explicit schedule.  `sched`
+ * may be NULL (library chooses).  Used by the autotuner and the tests. */
+gf2_status gf2_mul_sched(uint64_t* C, int64_t ldc, const uint64_t* A, int64_t lda, const uint64_t* B,
+                         int64_t ldb, int64_t m, int64_t k, int64_t n, int32_t accumulate,
+                         const gf2_schedule* sched, void* stream);
+
+/* Number of tile variants of a base kernel (0 for an unknown kernel). */
+int32_t gf2_kernel_variants(int32_t kernel);
+
+/* Device workspace, in bytes, that a product of this shape under `sched` uses
+ * (Strassen temporaries and split-K partials; 0 when none). */
+size_t gf2_workspace_bytes(int64_t m, int64_t k, int64_t n, const gf2_schedule* sched);
+
+/* Grow the current device's workspace to at least `bytes` now (synchronising
+ * the device), so that later calls -- for instance under stream capture --
+ * need no allocation. */
+gf2_status gf2_reserve_workspace(size_t bytes);
+
+const char* gf2_status_string(gf2_status s);
+/* Text of the last error raised on the calling thread ("" if none). */
+const char* gf2_last_error(void);
+
+/* Release every device and host resource the library holds, on all devices. */
+void gf2_shutdown(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GF2_H */

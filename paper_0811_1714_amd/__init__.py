@@ -1,0 +1,138 @@
+"""Dense matrix multiplication over GF(2) on AMD MI355X (gfx950).
+
+Thin ctypes binding over ``libgf2.so`` (see ``include/gf2.h``): argument
+marshalling only.  Every step of a product runs in the library's HIP kernels;
+there is no CPU fallback, and a missing library raises at first use.
+
+Matrices are PyTorch CUDA (HIP) tensors used as raw storage: 2-D, dtype
+``torch.int64`` (bit patterns of uint64 words), unit stride along rows;
+``ld`` is ``tensor.stride(0)``.  Column j of a row is bit j&63 of word j>>6.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgf2.so")
+_LIB = None
+
+KERNEL_AUTO, KERNEL_M4RM, KERNEL_MFMA, KERNEL_CUBIC = 0, 1, 2, 3
+
+STATUS = {0: "GF2_OK", 1: "GF2_ERR_INVALID_ARG", 2: "GF2_ERR_ALIAS", 3: "GF2_ERR_ALLOC", 4: "GF2_ERR_CAPTURE",
+          5: "GF2_ERR_DEVICE", 6: "GF2_ERR_UNSUPPORTED"}
+
+
+class GF2Error(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class Schedule(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_int32), ("variant", ctypes.c_int32), ("cutoff", ctypes.c_int32),
+                ("splitk", ctypes.c_int32)]
+
+    def __repr__(self):
+        return f"Schedule(kernel={self.kernel}, variant={self.variant}, cutoff={self.cutoff}, splitk={self.splitk})"
+
+
+def lib():
+    """Load libgf2.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_0811_1714_amd.build` "
+                           "(the GPU path has no fallback)")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I64, I32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+    mm = [P, I64, P, I64, P, I64, I64, I64, I64]
+    L.gf2_mul.argtypes = mm + [P]
+    L.gf2_addmul.argtypes = mm + [P]
+    L.gf2_mul_sched.argtypes = mm + [I32, ctypes.POINTER(Schedule), P]
+    for f in (L.gf2_mul, L.gf2_addmul, L.gf2_mul_sched):
+        f.restype = ctypes.c_int
+    L.gf2_kernel_variants.argtypes = [I32]
+    L.gf2_kernel_variants.restype = I32
+    L.gf2_workspace_bytes.argtypes = [I64, I64, I64, ctypes.POINTER(Schedule)]
+    L.gf2_workspace_bytes.restype = ctypes.c_size_t
+    L.gf2_reserve_workspace.argtypes = [ctypes.c_size_t]
+    L.gf2_reserve_workspace.restype = ctypes.c_int
+    L.gf2_status_string.argtypes = [ctypes.c_int]
+    L.gf2_status_string.restype = ctypes.c_char_p
+    L.gf2_last_error.restype = ctypes.c_char_p
+    L.gf2_shutdown.restype = None
+    _LIB = L
+    return L
+
+
+def _check(status: int):
+    if status != 0:
+        raise GF2Error(status, lib().gf2_last_error().decode())
+
+
+def last_error() -> str:
+    return lib().gf2_last_error().decode()
+
+
+def _stream_handle(stream):
+    if stream is None:
+        import torch
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _mat(t):
+    """(pointer, ld) of a 2-D int64 CUDA tensor with unit row stride."""
+    if t is None:
+        return ctypes.c_void_p(0), 0
+    if t.dim() != 2:
+        raise ValueError("matrices must be 2-D")
+    if t.numel() > 0 and t.shape[1] > 1 and t.stride(1) != 1:
+        raise ValueError("matrices must have unit stride along rows")
+    if t.element_size() != 8:
+        raise ValueError("matrices must hold 64-bit words (torch.int64)")
+    if not t.is_cuda:
+        raise ValueError("matrices must be on the GPU")
+    ld = t.stride(0) if t.shape[0] > 1 else t.shape[1]   # torch reports arbitrary strides for 0/1 rows
+    return ctypes.c_void_p(t.data_ptr()), ld
+
+
+def mul_ptr(C, ldc, A, lda, B, ldb, m, k, n, *, accumulate=False, schedule=None, stream=None):
+    """Raw-pointer form: C := A*B (or C ^= A*B).  Pointers are device addresses (ints)."""
+    L = lib()
+    s = _stream_handle(stream)
+    if schedule is None and not accumulate:
+        _check(L.gf2_mul(C, ldc, A, lda, B, ldb, m, k, n, s))
+    elif schedule is None:
+        _check(L.gf2_addmul(C, ldc, A, lda, B, ldb, m, k, n, s))
+    else:
+        _check(L.gf2_mul_sched(C, ldc, A, lda, B, ldb, m, k, n, int(accumulate), ctypes.byref(schedule), s))
+
+
+def mul(C, A, B, m, k, n, *, accumulate=False, schedule=None, stream=None):
+    """C := A*B over GF(2) (``accumulate=True``: C := C + A*B), on tensors."""
+    pc, ldc = _mat(C)
+    pa, lda = _mat(A)
+    pb, ldb = _mat(B)
+    mul_ptr(pc, ldc, pa, lda, pb, ldb, m, k, n, accumulate=accumulate, schedule=schedule, stream=stream)
+    return C
+
+
+def kernel_variants(kernel: int) -> int:
+    return int(lib().gf2_kernel_variants(kernel))
+
+
+def workspace_bytes(m, k, n, schedule=None) -> int:
+    return int(lib().gf2_workspace_bytes(m, k, n, ctypes.byref(schedule) if schedule is not None else None))
+
+
+def reserve_workspace(nbytes: int):
+    _check(lib().gf2_reserve_workspace(nbytes))
+
+
+def shutdown():
+    lib().gf2_shutdown()

@@ -1,0 +1,75 @@
+// Internal declarations shared by the library's translation units.
+// Not part of the public ABI (that is include/gf2.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <cstddef>
+#include "gf2.h"
+
+namespace gf2 {
+
+// How a kernel writes its result tile into C.
+enum OutMode : int32_t {
+  OUT_STORE = 0,    // C := P            (padding bits written 0)
+  OUT_XOR = 1,      // C := C ^ P        (non-atomic read-modify-write; padding unchanged)
+  OUT_ATOMIC = 2,   // C ^= P atomically (several producers of the same C words)
+};
+
+// One product C (m x n) <- A (m x k) * B (k x n), each a window of a row-major packed
+// matrix: ``ld`` words per row, column j of a row at bit j&63 of word j>>6.
+struct MulDesc {
+  const uint64_t* A;
+  const uint64_t* B;
+  uint64_t* C;
+  int64_t lda, ldb, ldc;
+  int32_t m, k, n;
+  int32_t out;        // OutMode
+};
+
+__host__ __device__ inline int64_t words(int64_t bits) { return (bits + 63) >> 6; }
+
+// Error reporting (thread-local text, read back through gf2_last_error()).
+gf2_status set_error(gf2_status s, const char* fmt, ...);
+gf2_status hip_check(hipError_t e, const char* what);
+
+// ---- kernels (each .hip file owns its launches) ----
+// Products launched together with descriptors passed by value in the kernel arguments.
+constexpr int kMaxGroup = 49;   // 7^2 Strassen leaves
+struct GroupArgs {
+  MulDesc d[kMaxGroup];
+  int tile_start[kMaxGroup + 1];
+  int count;
+};
+
+// M4RM base case (m4rm.hip).
+int m4rm_num_variants();
+int m4rm_tile_rows(int variant);
+int64_t m4rm_tiles(const MulDesc& d, int variant);
+gf2_status m4rm_launch_group(const MulDesc* descs, int count, int variant, hipStream_t s);
+gf2_status m4rm_launch_list(const MulDesc* dev_descs, const int* dev_tile_start, int count, int64_t total_tiles,
+                            int variant, hipStream_t s);
+
+// Element-wise XOR passes (xorops.hip).
+// A window of a packed matrix with virtual zero padding: rows >= rows and words >= wds
+// read as zero; the word wds-1 is ANDed with ``tail``.
+struct QView {
+  const uint64_t* p;
+  int64_t ld;
+  int64_t rows, wds;
+  uint64_t tail;
+};
+struct OView {
+  uint64_t* p;
+  int64_t ld;
+  int64_t rows, wds;   // region actually written
+  uint64_t tail;       // mask for word wds-1 (padding bits written 0 or left unchanged)
+};
+gf2_status fill_zero(const OView& o, hipStream_t s);
+// Strassen-Winograd pre-additions (Algorithm 4): from the four quadrants NW, NE, SW, SE
+// of A (kind 0) produce S0..S3, of B (kind 1) produce T0..T3, over R x Wd words.
+gf2_status strassen_pre(int kind, const QView in[4], uint64_t* const out[4], int64_t ldo, int64_t R, int64_t Wd,
+                        hipStream_t s);
+// Post-additions: from P0..P6 (R0 x W0 words each, ld ldp) write the four quadrants of C.
+gf2_status strassen_post(const uint64_t* const P[7], int64_t ldp, const OView c[4], int out_mode, hipStream_t s);
+
+}  // namespace gf2

@@ -1,0 +1,307 @@
+// M4RM base case for gfx950: the Method of the Four Russians (Section 3 of the
+// paper, Algorithms 1-3) with the Gray-code table build of Section 3.1.
+//
+// Mapping onto a CDNA4 compute unit:
+//  * A workgroup owns a C tile of BM = WAVES*RW rows by 2048 columns (32 words);
+//    the tile lives in VGPRs for the whole k loop and is written once (the row
+//    blocking of Algorithm 2, with registers in the role of the cache).
+//  * k is consumed in stripes of KB = 8 rows of B.  For each stripe the
+//    workgroup builds the table T[x] = XOR of rows kp+b of B with bit b of x set
+//    (all 2^8 combinations, 256 B per entry) in LDS, walking a Gray code so that
+//    every entry after the first costs one row addition.  Tables are double
+//    buffered: stripe p+1 is built while stripe p is looked up, one barrier per
+//    stripe.
+//  * Lookup ("ReadBits" + "AddRowFromTable"): byte p%4 of an A dword is the
+//    8-bit index of row r for stripe p (column j at bit j&63, so the index is
+//    LSB-first: bit b <-> row kp+b).  One v_perm builds the LDS address
+//    (index in byte 1, lane offset in byte 0, buffer in byte 2); one ds_read_b128
+//    serves four rows per wave instruction (16 lanes x 16 B = one 256 B entry
+//    per row), the pattern that measured fastest on gfx950 LDS.
+#include "gf2_internal.h"
+
+namespace gf2 {
+namespace {
+
+constexpr int KB = 8;                       // table width (kappa)
+constexpr int TILE_WORDS = 32;              // 2048 columns per tile
+constexpr int ENTRY_BYTES = TILE_WORDS * 8; // 256 B per table entry
+constexpr int TABLE_BYTES = (1 << KB) * ENTRY_BYTES;  // 64 KiB
+
+__device__ __forceinline__ uint4 xor4(uint4 a, uint4 b) {
+  return make_uint4(a.x ^ b.x, a.y ^ b.y, a.z ^ b.z, a.w ^ b.w);
+}
+
+// Raw buffer resource over [base, base + bytes): loads at offsets >= bytes return 0
+// (the hardware range check), which is how rows past k, rows past m and words past
+// the end of a row are read as zero without branches.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, int64_t bytes) {
+  const int nrec = bytes <= 0 ? 0 : (bytes >= 0x7fffffff ? 0x7fffffff : (int)bytes);
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, nrec, 0x00020000);
+}
+__device__ __forceinline__ uint2 bload2(__amdgpu_buffer_rsrc_t r, int off) {
+  return __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ __forceinline__ uint32_t bload1(__amdgpu_buffer_rsrc_t r, int off) {
+  return __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+}
+
+__device__ __forceinline__ void store_word(uint64_t* cp, uint64_t v, int out) {
+  if (out == OUT_STORE) {
+    *cp = v;
+  } else if (out == OUT_XOR) {
+    *cp ^= v;
+  } else {
+    if (v) atomicXor(reinterpret_cast<unsigned long long*>(cp), (unsigned long long)v);
+  }
+}
+
+// Workgroup-to-tile map: the hardware deals workgroups to the 8 XCDs round-robin;
+// give each XCD a contiguous range of logical tiles so that neighbouring tiles
+// (same B column panel) share that XCD's L2.
+__device__ __forceinline__ int xcd_remap(int i, int n) {
+  const int per = n / 8, rem = n % 8;
+  const int x = i % 8, idx = i / 8;
+  return x < rem ? x * (per + 1) + idx : rem * (per + 1) + (x - rem) * per + idx;
+}
+
+template <int WAVES, int RW>
+struct Tile {
+  static constexpr int S = RW / 4;          // row slots per lane (4 rows per wave instruction)
+  static constexpr int BM = WAVES * RW;
+  static constexpr int WB = WAVES == 16 ? 4 : WAVES == 8 ? 3 : WAVES == 4 ? 2 : 1;
+  static constexpr int LOWB = KB - WB - 2;  // entry bits walked along the Gray code by one lane
+  static_assert((1 << WB) == WAVES, "WAVES must be 2, 4, 8 or 16");
+  static_assert(RW % 8 == 0, "RW must be a multiple of 8");
+};
+
+// Build this lane's entries of one stripe's table into LDS buffer ``buf``.
+// Entry x (bit b <-> B row kp+b) = (w << (LOWB+2)) | (q << LOWB) | g(i), g the binary
+// reflected Gray code: consecutive i differ in exactly bit ctz(i), so each further
+// entry is the previous one plus one row of B (Section 3.1).
+// ``rb`` covers the stripe's rows of B from the tile's first word; rows past k and
+// words past the last valid word of the last row read as zero.
+template <int WAVES, int RW>
+__device__ __forceinline__ void build_table(char* tab, int buf, int w, int q, int l16, const uint64_t* pb,
+                                            int64_t ldb, int rows, int64_t row_bytes, int lane_off) {
+  using T = Tile<WAVES, RW>;
+  // One resource per row of the stripe: the row offset lives in the (uniform) base,
+  // rows past k get an empty range, so every lane uses the same small offset.
+  auto row = [&](int b) -> uint4 {
+    const __amdgpu_buffer_rsrc_t r = make_rsrc(pb + b * ldb, b < rows ? row_bytes : 0);
+    const uint2 lo = bload2(r, lane_off), hi = bload2(r, lane_off + 8);
+    return make_uint4(lo.x, lo.y, hi.x, hi.y);
+  };
+  uint4 v = make_uint4(0, 0, 0, 0);
+#pragma unroll
+  for (int b = T::LOWB + 2; b < KB; ++b)         // high bits: wave-uniform choice of rows
+    if ((w >> (b - T::LOWB - 2)) & 1) v = xor4(v, row(b));
+#pragma unroll
+  for (int b = T::LOWB; b < T::LOWB + 2; ++b) {  // middle bits: chosen per quarter-wave
+    const uint4 r = row(b);
+    if ((q >> (b - T::LOWB)) & 1) v = xor4(v, r);
+  }
+  uint4 low[T::LOWB > 0 ? T::LOWB : 1];
+#pragma unroll
+  for (int b = 0; b < T::LOWB; ++b) low[b] = row(b);
+  const uint32_t base = ((uint32_t)w << (T::LOWB + 2)) | ((uint32_t)q << T::LOWB);
+  char* dst = tab + ((uint32_t)buf << 16) + l16 * 16;
+  *reinterpret_cast<uint4*>(dst + base * ENTRY_BYTES) = v;
+#pragma unroll
+  for (int i = 1; i < (1 << T::LOWB); ++i) {
+    v = xor4(v, low[__builtin_ctz(i)]);
+    const uint32_t x = base | (uint32_t)(i ^ (i >> 1));
+    *reinterpret_cast<uint4*>(dst + x * ENTRY_BYTES) = v;
+  }
+}
+
+// One C tile of BM rows x 2048 columns.  EDGE = the tile reaches past the last row or
+// word of C, or its last word has padding bits: stores are guarded and masked.
+template <int WAVES, int RW, bool EDGE>
+__device__ __forceinline__ void m4rm_tile(const MulDesc& d, int tm, int tn, char* tab) {
+  using T = Tile<WAVES, RW>;
+  constexpr int S = T::S;
+  const int tid = threadIdx.x;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int L = tid & 63, q = L >> 4, l16 = L & 15;
+  const int64_t Wn = words(d.n);
+  const int lw = 2 * l16;                               // this lane's word offset inside the tile
+  const int64_t c0 = (int64_t)tn * TILE_WORDS;          // tile's first word column (uniform)
+  const int64_t Wt = Wn - c0;                           // valid words from the tile start
+  const int64_t row0 = (int64_t)tm * T::BM + (int64_t)w * RW;   // first row of this wave (uniform)
+  const int rows_here = (int)min<int64_t>(d.m - row0, RW);
+  const int nstripes = (d.k + KB - 1) / KB;
+  const int lda_b = (int)(d.lda * 8);
+  const int kdw = (d.k + 31) >> 5;                      // A dwords per row that hold bits < k
+  // A: this wave's rows; offsets past the last existing row read as zero.
+  const __amdgpu_buffer_rsrc_t ra =
+      make_rsrc(d.A + row0 * d.lda, rows_here > 0 ? (int64_t)(rows_here - 1) * lda_b + 4 * kdw : 0);
+  const uint32_t lanebase = (uint32_t)l16 * 16u;
+
+  uint4 acc[S];
+#pragma unroll
+  for (int s = 0; s < S; ++s) acc[s] = make_uint4(0, 0, 0, 0);
+
+  uint32_t aw[S], an[S];
+  auto load_a = [&](int g, uint32_t (&dst)[S]) {
+#pragma unroll
+    for (int s = 0; s < S; ++s) dst[s] = bload1(ra, (4 * s + q) * lda_b + 4 * g);
+  };
+  if (nstripes > 0) load_a(0, an);
+
+  auto build = [&](int p, int buf) {
+    const int64_t kp = (int64_t)p * KB;
+    const int rows = (int)min<int64_t>(d.k - kp, KB);
+    build_table<WAVES, RW>(tab, buf, w, q, l16, d.B + kp * d.ldb + c0, d.ldb, rows, 8 * Wt, lw * 8);
+  };
+  if (nstripes > 0) build(0, 0);
+  __syncthreads();
+
+  for (int p = 0; p < nstripes; ++p) {
+    if ((p & 3) == 0) {
+#pragma unroll
+      for (int s = 0; s < S; ++s) aw[s] = an[s];
+      if (p + 4 < nstripes) load_a((p >> 2) + 1, an);
+    }
+    const int buf = p & 1;
+    const uint32_t lb = lanebase | ((uint32_t)buf << 16);
+    const uint32_t sel = 0x0c020400u + ((uint32_t)(p & 3) << 8);  // byte0 <- lb, byte1 <- A byte, byte2 <- lb
+#pragma unroll
+    for (int s0 = 0; s0 < S; s0 += 4) {
+#pragma unroll
+      for (int s = s0; s < s0 + 4 && s < S; ++s) {
+        const uint32_t addr = __builtin_amdgcn_perm(aw[s], lb, sel);
+        acc[s] = xor4(acc[s], *reinterpret_cast<const uint4*>(tab + addr));
+      }
+      // Register fence: the XORs of this group complete here, so at most four
+      // lookups are in flight and none is held across the table build.
+#pragma unroll
+      for (int s = s0; s < s0 + 4 && s < S; ++s)
+        asm volatile("" : "+v"(acc[s].x), "+v"(acc[s].y), "+v"(acc[s].z), "+v"(acc[s].w));
+    }
+    if (p + 1 < nstripes) build(p + 1, buf ^ 1);
+    __syncthreads();
+  }
+
+  // Store: rows < m, words < Wn; padding bits of the last word are cleared.
+  const uint64_t tail = (d.n & 63) ? ((1ull << (d.n & 63)) - 1) : ~0ull;
+  const uint64_t m0 = (EDGE && lw == Wt - 1) ? tail : ~0ull;
+  const uint64_t m1 = (EDGE && lw + 1 == Wt - 1) ? tail : ~0ull;
+  uint64_t* pc = d.C + row0 * d.ldc + c0 + lw;
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const int rr = 4 * s + q;
+    if (!EDGE || rr < rows_here) {
+      uint64_t* cp = pc + (int64_t)rr * d.ldc;
+      const uint64_t w0 = ((uint64_t)acc[s].x | ((uint64_t)acc[s].y << 32)) & m0;
+      const uint64_t w1 = ((uint64_t)acc[s].z | ((uint64_t)acc[s].w << 32)) & m1;
+      if (!EDGE || lw < Wt) store_word(cp, w0, d.out);
+      if (!EDGE || lw + 1 < Wt) store_word(cp + 1, w1, d.out);
+    }
+  }
+}
+
+template <int WAVES, int RW>
+__device__ __forceinline__ void m4rm_tile_any(const MulDesc& d, int tm, int tn, char* tab) {
+  using T = Tile<WAVES, RW>;
+  const int64_t Wn = words(d.n);
+  const bool edge = (int64_t)(tm + 1) * T::BM > d.m || (int64_t)(tn + 1) * TILE_WORDS > Wn ||
+                    ((d.n & 63) != 0 && (int64_t)(tn + 1) * TILE_WORDS == Wn);
+  if (edge) m4rm_tile<WAVES, RW, true>(d, tm, tn, tab);
+  else m4rm_tile<WAVES, RW, false>(d, tm, tn, tab);
+}
+
+// Up to kMaxGroup products in one launch, descriptors passed by value (no device
+// staging, so the launch can be captured into a graph as is).  Workgroup b belongs to
+// the product i with tile_start[i] <= b < tile_start[i+1].
+template <int WAVES, int RW>
+__global__ __launch_bounds__(WAVES * 64) void m4rm_group(GroupArgs g) {
+  __shared__ uint4 tab[2 * TABLE_BYTES / 16];
+  const int t = xcd_remap(blockIdx.x, gridDim.x);
+  int i = 0;
+  while (i + 1 < g.count && g.tile_start[i + 1] <= t) ++i;
+  const MulDesc& d = g.d[i];
+  const int local = t - g.tile_start[i];
+  const int tiles_m = (d.m + Tile<WAVES, RW>::BM - 1) / Tile<WAVES, RW>::BM;
+  m4rm_tile_any<WAVES, RW>(d, local % tiles_m, local / tiles_m, reinterpret_cast<char*>(tab));
+}
+
+// Descriptor list in device memory (batched products).
+template <int WAVES, int RW>
+__global__ __launch_bounds__(WAVES * 64) void m4rm_list(const MulDesc* __restrict__ ds,
+                                                        const int* __restrict__ tile_start, int count) {
+  __shared__ uint4 tab[2 * TABLE_BYTES / 16];
+  const int t = xcd_remap(blockIdx.x, gridDim.x);
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (tile_start[mid] <= t) lo = mid; else hi = mid - 1;
+  }
+  const MulDesc d = ds[lo];
+  const int local = t - tile_start[lo];
+  const int tiles_m = (d.m + Tile<WAVES, RW>::BM - 1) / Tile<WAVES, RW>::BM;
+  m4rm_tile_any<WAVES, RW>(d, local % tiles_m, local / tiles_m, reinterpret_cast<char*>(tab));
+}
+
+struct Variant {
+  int waves, rw;
+  void (*group)(GroupArgs);
+  void (*list)(const MulDesc*, const int*, int);
+};
+
+#define GF2_M4RM_VARIANT(W, R) { W, R, m4rm_group<W, R>, m4rm_list<W, R> }
+const Variant kVariants[] = {
+    GF2_M4RM_VARIANT(16, 48),   // 0: BM 768, 16 waves
+    GF2_M4RM_VARIANT(8, 96),    // 1: BM 768, 8 waves
+    GF2_M4RM_VARIANT(16, 32),   // 2: BM 512
+    GF2_M4RM_VARIANT(8, 32),    // 3: BM 256
+    GF2_M4RM_VARIANT(4, 32),    // 4: BM 128
+};
+#undef GF2_M4RM_VARIANT
+constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
+
+const Variant& variant_of(int v) { return kVariants[(v < 0 || v >= kNumVariants) ? 0 : v]; }
+
+}  // namespace
+
+int m4rm_num_variants() { return kNumVariants; }
+int m4rm_tile_rows(int variant) { return variant_of(variant).waves * variant_of(variant).rw; }
+
+int64_t m4rm_tiles(const MulDesc& d, int variant) {
+  const int64_t bm = m4rm_tile_rows(variant);
+  return ((d.m + bm - 1) / bm) * ((words(d.n) + TILE_WORDS - 1) / TILE_WORDS);
+}
+
+gf2_status m4rm_launch_group(const MulDesc* descs, int count, int variant, hipStream_t s) {
+  const Variant& v = variant_of(variant);
+  for (int base = 0; base < count; base += kMaxGroup) {
+    GroupArgs g;
+    g.count = 0;
+    int64_t total = 0;
+    for (int i = base; i < count && g.count < kMaxGroup; ++i) {
+      const int64_t t = m4rm_tiles(descs[i], variant);
+      if (t == 0) continue;
+      g.d[g.count] = descs[i];
+      g.tile_start[g.count] = (int)total;
+      ++g.count;
+      total += t;
+      if (total > INT32_MAX) return set_error(GF2_ERR_UNSUPPORTED, "m4rm: too many tiles in one launch");
+    }
+    if (g.count == 0) continue;
+    g.tile_start[g.count] = (int)total;
+    hipLaunchKernelGGL(v.group, dim3((unsigned)total), dim3(v.waves * 64), 0, s, g);
+    gf2_status st = hip_check(hipGetLastError(), "m4rm_group launch");
+    if (st != GF2_OK) return st;
+  }
+  return GF2_OK;
+}
+
+gf2_status m4rm_launch_list(const MulDesc* dev_descs, const int* dev_tile_start, int count, int64_t total_tiles,
+                            int variant, hipStream_t s) {
+  if (total_tiles == 0 || count == 0) return GF2_OK;
+  if (total_tiles > INT32_MAX) return set_error(GF2_ERR_UNSUPPORTED, "m4rm: too many tiles");
+  const Variant& v = variant_of(variant);
+  hipLaunchKernelGGL(v.list, dim3((unsigned)total_tiles), dim3(v.waves * 64), 0, s, dev_descs, dev_tile_start, count);
+  return hip_check(hipGetLastError(), "m4rm_list launch");
+}
+
+}  // namespace gf2

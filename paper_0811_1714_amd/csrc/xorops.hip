@@ -1,0 +1,139 @@
+// Element-wise passes over packed GF(2) matrices: bulk zeroing and the fused
+// pre- and post-additions of Strassen-Winograd (Section 4, Algorithm 4).
+// Over GF(2) addition and subtraction are both XOR (Section 2.2: a row addition
+// is a word-wise XOR).  These passes are bound by HBM bandwidth: each thread
+// handles one 64-bit word position, consecutive threads consecutive words.
+#include "gf2_internal.h"
+
+namespace gf2 {
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ uint64_t qload(const QView& v, int64_t r, int64_t w) {
+  if (r >= v.rows || w >= v.wds) return 0;
+  uint64_t x = v.p[r * v.ld + w];
+  return w == v.wds - 1 ? (x & v.tail) : x;
+}
+
+__device__ __forceinline__ void owrite(const OView& o, int64_t r, int64_t w, uint64_t x, int mode) {
+  if (r >= o.rows || w >= o.wds) return;
+  if (w == o.wds - 1) x &= o.tail;
+  uint64_t* p = o.p + r * o.ld + w;
+  *p = mode == OUT_STORE ? x : (*p ^ x);
+}
+
+__global__ void fill_zero_kernel(OView o) {
+  const int64_t total = o.rows * o.wds;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / o.wds, w = i - r * o.wds;
+    o.p[r * o.ld + w] = 0;
+  }
+}
+
+struct PreArgs {
+  QView in[4];          // NW, NE, SW, SE
+  uint64_t* out[4];     // S0..S3 or T0..T3
+  int64_t ldo, R, Wd;
+};
+
+// kind 0 (A):  S0 = SW+SE, S1 = S0+NW, S2 = NW+SW, S3 = NE+S1
+// kind 1 (B):  T0 = NE+NW, T1 = SE+T0, T2 = SE+NE, T3 = T1+SW
+template <int KIND>
+__global__ void strassen_pre_kernel(PreArgs a) {
+  const int64_t total = a.R * a.Wd;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / a.Wd, w = i - r * a.Wd;
+    const uint64_t nw = qload(a.in[0], r, w), ne = qload(a.in[1], r, w);
+    const uint64_t sw = qload(a.in[2], r, w), se = qload(a.in[3], r, w);
+    uint64_t o0, o1, o2, o3;
+    if (KIND == 0) {
+      o0 = sw ^ se;
+      o1 = o0 ^ nw;
+      o2 = nw ^ sw;
+      o3 = ne ^ o1;
+    } else {
+      o0 = ne ^ nw;
+      o1 = se ^ o0;
+      o2 = se ^ ne;
+      o3 = o1 ^ sw;
+    }
+    const int64_t off = r * a.ldo + w;
+    a.out[0][off] = o0;
+    a.out[1][off] = o1;
+    a.out[2][off] = o2;
+    a.out[3][off] = o3;
+  }
+}
+
+struct PostArgs {
+  const uint64_t* P[7];
+  int64_t ldp;
+  OView c[4];           // C_NW, C_NE, C_SW, C_SE (their written regions)
+  int mode;
+};
+
+// U0 = P0+P1, U1 = P0+P5, U2 = U1+P6, U3 = U1+P4, U4 = U3+P2, U5 = U2+P3, U6 = U2+P4;
+// C_NW = U0, C_NE = U4, C_SW = U5, C_SE = U6.  The grid covers C_NW's region, which
+// contains the other three (top/left halves are the larger ones).
+__global__ void strassen_post_kernel(PostArgs a) {
+  const int64_t R = a.c[0].rows, Wd = a.c[0].wds, total = R * Wd;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / Wd, w = i - r * Wd;
+    const int64_t off = r * a.ldp + w;
+    const bool ne = r < a.c[1].rows && w < a.c[1].wds;
+    const bool sw = r < a.c[2].rows && w < a.c[2].wds;
+    const bool se = r < a.c[3].rows && w < a.c[3].wds;
+    const uint64_t p0 = a.P[0][off];
+    owrite(a.c[0], r, w, p0 ^ a.P[1][off], a.mode);
+    if (ne || sw || se) {
+      const uint64_t u1 = p0 ^ a.P[5][off];
+      const uint64_t p4 = (ne || se) ? a.P[4][off] : 0;
+      if (ne) owrite(a.c[1], r, w, u1 ^ p4 ^ a.P[2][off], a.mode);
+      if (sw || se) {
+        const uint64_t u2 = u1 ^ a.P[6][off];
+        if (sw) owrite(a.c[2], r, w, u2 ^ a.P[3][off], a.mode);
+        if (se) owrite(a.c[3], r, w, u2 ^ p4, a.mode);
+      }
+    }
+  }
+}
+
+unsigned grid_for(int64_t total) {
+  int64_t b = (total + kThreads - 1) / kThreads;
+  const int64_t cap = 256 * 16;
+  return (unsigned)(b < 1 ? 1 : (b > cap ? cap : b));
+}
+
+}  // namespace
+
+gf2_status fill_zero(const OView& o, hipStream_t s) {
+  if (o.rows <= 0 || o.wds <= 0) return GF2_OK;
+  hipLaunchKernelGGL(fill_zero_kernel, dim3(grid_for(o.rows * o.wds)), dim3(kThreads), 0, s, o);
+  return hip_check(hipGetLastError(), "fill_zero launch");
+}
+
+gf2_status strassen_pre(int kind, const QView in[4], uint64_t* const out[4], int64_t ldo, int64_t R, int64_t Wd,
+                        hipStream_t s) {
+  if (R <= 0 || Wd <= 0) return GF2_OK;
+  PreArgs a;
+  for (int i = 0; i < 4; ++i) { a.in[i] = in[i]; a.out[i] = out[i]; }
+  a.ldo = ldo; a.R = R; a.Wd = Wd;
+  if (kind == 0) hipLaunchKernelGGL(strassen_pre_kernel<0>, dim3(grid_for(R * Wd)), dim3(kThreads), 0, s, a);
+  else hipLaunchKernelGGL(strassen_pre_kernel<1>, dim3(grid_for(R * Wd)), dim3(kThreads), 0, s, a);
+  return hip_check(hipGetLastError(), "strassen_pre launch");
+}
+
+gf2_status strassen_post(const uint64_t* const P[7], int64_t ldp, const OView c[4], int out_mode, hipStream_t s) {
+  PostArgs a;
+  for (int i = 0; i < 7; ++i) a.P[i] = P[i];
+  for (int i = 0; i < 4; ++i) a.c[i] = c[i];
+  a.ldp = ldp;
+  a.mode = out_mode;
+  const int64_t total = c[0].rows * c[0].wds;
+  if (total <= 0) return GF2_OK;
+  hipLaunchKernelGGL(strassen_post_kernel, dim3(grid_for(total)), dim3(kThreads), 0, s, a);
+  return hip_check(hipGetLastError(), "strassen_post launch");
+}
+
+}  // namespace gf2

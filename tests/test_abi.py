@@ -1,0 +1,89 @@
+"""The C ABI without a GPU: the library loads, exports every function include/gf2.h declares,
+and rejects bad arguments with the documented status before touching a device."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+import paper_0811_1714_amd as g
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    names = set()
+    for h in os.listdir(os.path.join(ROOT, "include")):
+        if not h.endswith(".h"):
+            continue
+        text = open(os.path.join(ROOT, "include", h)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for mt in re.finditer(r"\b(gf2_[a-z0-9_]+)\s*\(", text):
+            names.add(mt.group(1))
+    return sorted(names)
+
+
+def test_library_exports_every_declared_function():
+    names = declared_functions()
+    assert "gf2_mul" in names and "gf2_addmul" in names
+    out = subprocess.run(["nm", "-D", "--defined-only", g.LIB_PATH], capture_output=True, text=True, check=True).stdout
+    exported = {ln.split()[-1] for ln in out.splitlines() if " T " in ln}
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    L = g.lib()
+    for n in names:
+        assert hasattr(L, n)
+
+
+P = ctypes.c_void_p
+
+
+def call(m, k, n, C=0x10000, ldc=2, A=0x20000, lda=2, B=0x30000, ldb=2, fn="gf2_mul"):
+    return getattr(g.lib(), fn)(P(C), ldc, P(A), lda, P(B), ldb, m, k, n, None)
+
+
+@pytest.mark.parametrize("fn", ["gf2_mul", "gf2_addmul"])
+def test_validation_codes(fn):
+    INV, ALIAS, UNSUP = 1, 2, 6
+    assert call(-1, 5, 5, fn=fn) == INV
+    assert call(5, -1, 5, fn=fn) == INV
+    assert call(5, 5, -1, fn=fn) == INV
+    assert call(5, 100, 5, lda=1, fn=fn) == INV          # lda < ceil(k/64)
+    assert call(5, 5, 200, ldb=3, ldc=4, fn=fn) == INV   # ldb < ceil(n/64)
+    assert call(5, 5, 200, ldb=4, ldc=3, fn=fn) == INV   # ldc < ceil(n/64)
+    assert call(5, 5, 5, C=0, fn=fn) == INV
+    assert call(5, 5, 5, A=0, fn=fn) == INV
+    assert call(5, 5, 5, B=0, fn=fn) == INV
+    assert call(5, 5, 5, C=0x10004, fn=fn) == INV        # misaligned
+    assert call(5, 5, 5, A=0x20001, fn=fn) == INV
+    assert call(5, 5, 5, C=0x20008, fn=fn) == ALIAS      # C inside A
+    assert call(5, 5, 5, C=0x30000, fn=fn) == ALIAS      # C == B
+    assert call(1 << 31, 5, 5, fn=fn) == UNSUP
+    assert call(5, 5, 5, ldc=1 << 22, fn=fn) == UNSUP
+    assert g.last_error() != ""
+    # empty products are no-ops that never touch the device
+    assert call(0, 5, 5, fn=fn) == 0
+    assert call(5, 5, 0, fn=fn) == 0
+
+
+def test_schedule_validation():
+    L = g.lib()
+    bad = [g.Schedule(9, 0, 0, 1), g.Schedule(g.KERNEL_M4RM, 99, 0, 1), g.Schedule(g.KERNEL_M4RM, 0, -1, 1),
+           g.Schedule(g.KERNEL_M4RM, 0, 0, 1000)]
+    for s in bad:
+        r = L.gf2_mul_sched(P(0x10000), 2, P(0x20000), 2, P(0x30000), 2, 5, 5, 5, 0, ctypes.byref(s), None)
+        assert r in (1, 6), (s, r)
+
+
+def test_status_strings():
+    L = g.lib()
+    for code, name in g.STATUS.items():
+        assert L.gf2_status_string(code).decode() == name
+
+
+def test_workspace_sizing_matches_plan():
+    # Strassen-Winograd, one level on 1024^3: 4 S (512x8 words), 4 T (512x8), 7 P (512x8) buffers.
+    s = g.Schedule(g.KERNEL_M4RM, 0, 512, 1)
+    assert g.workspace_bytes(1024, 1024, 1024, s) == 15 * 512 * 8 * 8
+    assert g.workspace_bytes(1024, 1024, 1024, g.Schedule(g.KERNEL_M4RM, 0, 0, 1)) == 0

@@ -1,0 +1,84 @@
+"""GPU parity of the M4RM base case, split-K and Strassen-Winograd against the CPU oracle.
+
+Every comparison is bit-exact: over GF(2) the product is unique.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from gf2_testutil import run_and_check
+
+
+@pytest.fixture(scope="module")
+def g():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_0811_1714_amd as g
+    g.lib()
+    return g
+
+
+def M4RM(variant=0, cutoff=0, splitk=1):
+    import paper_0811_1714_amd as g
+    return g.Schedule(g.KERNEL_M4RM, variant, cutoff, splitk)
+
+
+def test_config_1024_square_plain_m4rm(g):
+    # 1024 x 1024 times 1024 x 1024, Bernoulli(1/2), M4RM with 8-bit tables, no Strassen.
+    for v in range(g.kernel_variants(g.KERNEL_M4RM)):
+        print(f"1024^3 variant {v}", flush=True)
+        run_and_check(g, 1024, 1024, 1024, schedule=M4RM(v), garbage=False, seed=0)
+
+
+SHAPES = [(1, 1, 1), (1, 64, 64), (7, 9, 130), (64, 64, 64), (65, 65, 65), (127, 200, 63), (129, 129, 129),
+          (300, 777, 129), (1000, 513, 2049), (769, 1025, 2048), (2047, 31, 4097), (33, 5000, 70)]
+
+
+@pytest.mark.parametrize("m,k,n", SHAPES)
+def test_shape_grid_all_variants(g, m, k, n):
+    for v in range(g.kernel_variants(g.KERNEL_M4RM)):
+        print(f"shape {(m, k, n)} variant {v}", flush=True)
+        run_and_check(g, m, k, n, schedule=M4RM(v), seed=m + k + n, lda_pad=1, ldb_pad=3, ldc_pad=2)
+
+
+@pytest.mark.parametrize("m,k,n", [(100, 300, 70), (513, 2048, 2100), (64, 65, 4096)])
+def test_addmul_semantics(g, m, k, n):
+    print(f"addmul {(m, k, n)}", flush=True)
+    run_and_check(g, m, k, n, schedule=M4RM(0), accumulate=True, seed=3, ldc_pad=1)
+    run_and_check(g, m, k, n, accumulate=True, seed=4)
+
+
+@pytest.mark.parametrize("m,k,n,sk", [(100, 4096, 129, 4), (4095, 6553, 129, 32), (300, 1000, 3000, 7)])
+def test_split_k(g, m, k, n, sk):
+    print(f"split-k {(m, k, n, sk)}", flush=True)
+    run_and_check(g, m, k, n, schedule=M4RM(2, 0, sk), seed=5, ldc_pad=1)
+    run_and_check(g, m, k, n, schedule=M4RM(2, 0, sk), accumulate=True, seed=6)
+
+
+@pytest.mark.parametrize("m,k,n,cutoff", [(256, 256, 256, 64), (300, 200, 500, 64), (1000, 1000, 1000, 100),
+                                          (777, 1500, 1300, 300), (2049, 2049, 2049, 512), (1025, 130, 1025, 64)])
+def test_strassen_winograd_any_cutoff_same_bits(g, m, k, n, cutoff):
+    print(f"strassen {(m, k, n)} cutoff {cutoff}", flush=True)
+    base = run_and_check(g, m, k, n, schedule=M4RM(0, 0), seed=7)
+    got = run_and_check(g, m, k, n, schedule=M4RM(0, cutoff), seed=7)
+    assert np.array_equal(base, got)
+    run_and_check(g, m, k, n, schedule=M4RM(3, cutoff), seed=8, accumulate=True, ldc_pad=1)
+
+
+def test_degenerate_shapes(g):
+    for (m, k, n) in [(0, 5, 5), (5, 0, 5), (5, 5, 0), (1, 0, 1), (3, 1, 1), (1, 1, 200)]:
+        print(f"degenerate {(m, k, n)}", flush=True)
+        run_and_check(g, m, k, n, seed=9, ldc_pad=1)
+        run_and_check(g, m, k, n, seed=9, accumulate=True)
+
+
+def test_sparse_inputs(g):
+    print("p = 0.01", flush=True)
+    run_and_check(g, 1000, 3000, 2000, p=0.01, seed=10)
+
+
+def test_repeat_runs_identical(g):
+    print("repeat", flush=True)
+    run_and_check(g, 1500, 1500, 1500, schedule=M4RM(1), seed=11, repeat=3)
