@@ -1,0 +1,197 @@
+"""Benchmark: dense GF(2) products on one MI355X.
+
+One step = one n x n by n x n product over GF(2) (default n = 32768, the
+largest square workload), computed by the library's schedule for that shape
+(Strassen-Winograd over the M4RM base case), on uniformly random bits
+(Bernoulli(1/2), splitmix64-seeded, inputs resident in HBM before timing).
+
+Prints one JSON line.  ``value`` is effective bit-operations per second,
+2*n^3 / (seconds per product) -- one AND and one XOR per inner-product term.
+``roofline`` reports the dominant kernel (the M4RM leaves), timed live with HIP
+event pairs the library records around each of its launches.  ``cpu_baseline``
+times the CPU oracle on a bounded sample of rows of the same product.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+LDS_PEAK = 256 * 2.4e9 * 256            # bytes/s: 64 banks x 4 B per clock, 256 CUs, 2.4 GHz
+VALU_WORD_XOR_PEAK = 256 * 64 * 2.4e9   # 64-bit table-row additions/s at one v_bitop3 per 2 words per lane
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=32768)
+    ap.add_argument("--variant", type=int, default=None)
+    ap.add_argument("--cutoff", type=int, default=None)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--sweep", action="store_true", help="time candidate schedules for n = 8K, 16K, 32K")
+    ap.add_argument("--sweep-n", type=int, nargs="*", default=None)
+    ap.add_argument("--check-rows", type=int, default=16, help="rows compared with the oracle after timing")
+    return ap.parse_args()
+
+
+def default_schedule(g, n):
+    """Schedule used for the headline: tuned on MI355X."""
+    return g.Schedule(g.KERNEL_M4RM, 0, 0, 1)
+
+
+def to_dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a).view(np.int64)).cuda()
+
+
+def time_product(g, dA, dB, dC, n, sched, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        g.mul(dC, dA, dB, n, n, n, schedule=sched)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    evs[0].record(stream)
+    for i in range(steps):
+        g.mul(dC, dA, dB, n, n, n, schedule=sched)
+        evs[i + 1].record(stream)
+    torch.cuda.synchronize()
+    per = [evs[i].elapsed_time(evs[i + 1]) for i in range(steps)]
+    total = evs[0].elapsed_time(evs[-1])
+    return total / steps, per
+
+
+SWEEP_N = (8192, 16384, 32768)
+
+
+def sweep(g):
+    import torch
+    import synth
+    for n in SWEEP_N:
+        A = synth.uniform(1, synth.TAG_A, n, n)
+        B = synth.uniform(1, synth.TAG_B, n, n)
+        dA, dB = to_dev(A), to_dev(B)
+        dC = torch.empty_like(dA)
+        for cutoff in (0, n // 2, n // 4):
+            if cutoff and cutoff < 2048 or (cutoff == n // 2 and n > 8192):
+                continue
+            for v in range(g.kernel_variants(g.KERNEL_M4RM)):
+                s = g.Schedule(g.KERNEL_M4RM, v, cutoff, 1)
+                ms, per = time_product(g, dA, dB, dC, n, s, 3, 1)
+                print(json.dumps({"n": n, "variant": v, "cutoff": cutoff, "ms": round(min(per), 4),
+                                  "eff_bitops": 2 * n ** 3 / (min(per) * 1e-3)}), flush=True)
+        del dA, dB, dC
+        torch.cuda.empty_cache()
+
+
+def cpu_baseline(A, B, n, seconds):
+    import oracle
+    threads = oracle.max_threads()
+    rows = 8
+    t0 = time.perf_counter()
+    oracle.mul_rows(A, B, n, n, n, np.arange(rows), nthreads=threads)
+    dt = time.perf_counter() - t0
+    rows = int(max(8, min(n, rows * seconds / max(dt, 1e-6))))
+    sel = np.arange(rows) * (n // rows)
+    t0 = time.perf_counter()
+    oracle.mul_rows(A, B, n, n, n, sel, nthreads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": 2.0 * rows * n * n / dt, "unit": "bit-ops/s", "cores": threads, "kind": "oracle",
+            "sample": f"{rows} of {n} rows of the n={n} product (row-by-row packed XOR), {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md for how it would "
+              "shard); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_0811_1714_amd as g
+    import synth
+    import oracle
+
+    g.lib()
+    if args.sweep:
+        global SWEEP_N
+        if args.sweep_n:
+            SWEEP_N = tuple(args.sweep_n)
+        sweep(g)
+        return
+    n = args.n
+    sched = default_schedule(g, n)
+    if args.variant is not None:
+        sched.variant = args.variant
+    if args.cutoff is not None:
+        sched.cutoff = args.cutoff
+    A = synth.uniform(1, synth.TAG_A, n, n)
+    B = synth.uniform(1, synth.TAG_B, n, n)
+    dA, dB = to_dev(A), to_dev(B)
+    dC = torch.empty_like(dA)
+    ws = g.workspace_bytes(n, n, n, sched)
+    if ws:
+        g.reserve_workspace(ws)
+
+    for _ in range(args.warmup):
+        g.mul(dC, dA, dB, n, n, n, schedule=sched)
+    torch.cuda.synchronize()
+    g.trace_clear()
+    g.trace_enable(True)
+    ms, per = time_product(g, dA, dB, dC, n, sched, args.steps, 0)
+    g.trace_enable(False)
+    recs = g.trace_read()
+    g.trace_clear()
+
+    # correctness of what was timed: sampled rows against the oracle
+    rows = np.unique(np.linspace(0, n - 1, max(2, args.check_rows)).astype(np.int64))
+    got = dC.cpu().numpy().view(np.uint64)[rows]
+    ref = oracle.mul_rows(A, B, n, n, n, rows)
+    exact = bool(np.array_equal(got, ref))
+
+    m4 = [r for r in recs if r[0] == "m4rm"]
+    launches = len(m4)
+    work = sum(r[2] for r in m4) / max(1, launches)
+    kms = sum(r[3] for r in m4) / max(1, launches)
+    achieved = 8.0 * work / (kms * 1e-3)   # LDS bytes: each 64-bit table-row addition reads 8 B of table
+    out = {
+        "metric": "ms and effective GF(2) bit-ops/s per n x n product, % roofline",
+        "value": 2.0 * n ** 3 / (ms * 1e-3),
+        "unit": "bit-ops/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64 (bit-packed GF(2))",
+        "data": "synthetic",
+        "config": {"workload": f"square GF(2) product n={n}, Bernoulli(1/2) bits, packed 64 per word",
+                   "n": n, "schedule": {"kernel": "m4rm", "variant": sched.variant, "cutoff": sched.cutoff,
+                                        "splitk": sched.splitk},
+                   "ms_min": min(per), "ms_median": float(np.median(per)), "bit_exact_sampled_rows": exact},
+        "roofline": {"bound": "lds", "kernel": "m4rm leaves", "achieved": achieved / 1e9, "peak": LDS_PEAK / 1e9,
+                     "unit": "GB/s", "frac": achieved / LDS_PEAK, "traffic": None,
+                     "launches_per_step": launches / max(1, args.steps), "kernel_ms": kms,
+                     "word_xors_per_launch": work,
+                     "valu_roof_frac": (work / VALU_WORD_XOR_PEAK) / (kms * 1e-3)},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(A, B, n, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+    if not exact:
+        sys.exit(1)
+
+
+if __name__ == "__main__":
+    main()

@@ -102,6 +102,32 @@ size_t gf2_workspace_bytes(int64_t m, int64_t k, int64_t n, const gf2_schedule* 
  * need no allocation. */
 gf2_status gf2_reserve_workspace(size_t bytes);
 
+/* ---- Launch tracing (for measurement; off by default) ----
+ * While enabled, the library brackets every kernel launch with a pair of HIP
+ * events on the launch's stream and records the kernel kind and its
+ * algorithmic work.  gf2_trace_read synchronises those events.  Not for use
+ * under stream capture. */
+enum {
+  GF2_TRACE_M4RM = 1,   /* work = 64-bit table-row additions m*ceil(k/8)*ceil(n/64) */
+  GF2_TRACE_MFMA = 2,   /* work = multiply-accumulates m*k*n */
+  GF2_TRACE_CUBIC = 3,  /* work = 64-bit AND+popcount steps m*n*ceil(k/64) */
+  GF2_TRACE_PRE = 4,    /* work = bytes moved by the Strassen pre-additions */
+  GF2_TRACE_POST = 5,   /* work = bytes moved by the Strassen post-additions */
+  GF2_TRACE_FILL = 6,   /* work = bytes written */
+  GF2_TRACE_BATCH = 7   /* work = 64-bit table-row additions of a batched launch */
+};
+typedef struct gf2_trace_record {
+  int32_t kind;    /* GF2_TRACE_* */
+  int32_t items;   /* products (or passes) in the launch */
+  double work;     /* algorithmic work of the launch, unit per kind */
+  double ms;       /* launch duration from its event pair */
+} gf2_trace_record;
+gf2_status gf2_trace_enable(int32_t on);
+/* Copies up to `max` records (oldest first) into `out` and sets *count to the number
+ * copied; synchronises the recorded events.  Records stay until gf2_trace_clear. */
+gf2_status gf2_trace_read(gf2_trace_record* out, int64_t max, int64_t* count);
+void gf2_trace_clear(void);
+
 const char* gf2_status_string(gf2_status s);
 /* Text of the last error raised on the calling thread ("" if none). */
 const char* gf2_last_error(void);

@@ -63,6 +63,11 @@ def lib():
     L.gf2_status_string.restype = ctypes.c_char_p
     L.gf2_last_error.restype = ctypes.c_char_p
     L.gf2_shutdown.restype = None
+    L.gf2_trace_enable.argtypes = [I32]
+    L.gf2_trace_enable.restype = ctypes.c_int
+    L.gf2_trace_read.argtypes = [ctypes.c_void_p, I64, ctypes.POINTER(I64)]
+    L.gf2_trace_read.restype = ctypes.c_int
+    L.gf2_trace_clear.restype = None
     _LIB = L
     return L
 
@@ -120,6 +125,29 @@ def mul(C, A, B, m, k, n, *, accumulate=False, schedule=None, stream=None):
     pb, ldb = _mat(B)
     mul_ptr(pc, ldc, pa, lda, pb, ldb, m, k, n, accumulate=accumulate, schedule=schedule, stream=stream)
     return C
+
+
+class TraceRecord(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("items", ctypes.c_int32), ("work", ctypes.c_double), ("ms", ctypes.c_double)]
+
+
+TRACE_KINDS = {1: "m4rm", 2: "mfma", 3: "cubic", 4: "strassen_pre", 5: "strassen_post", 6: "fill", 7: "batch"}
+
+
+def trace_enable(on: bool = True):
+    _check(lib().gf2_trace_enable(int(on)))
+
+
+def trace_read(max_records: int = 1 << 16):
+    """List of (kind name, items, work, ms) for launches recorded since the last clear."""
+    buf = (TraceRecord * max_records)()
+    cnt = ctypes.c_int64(0)
+    _check(lib().gf2_trace_read(buf, max_records, ctypes.byref(cnt)))
+    return [(TRACE_KINDS.get(r.kind, str(r.kind)), r.items, r.work, r.ms) for r in buf[:cnt.value]]
+
+
+def trace_clear():
+    lib().gf2_trace_clear()
 
 
 def kernel_variants(kernel: int) -> int:

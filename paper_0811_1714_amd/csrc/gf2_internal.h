@@ -32,6 +32,19 @@ __host__ __device__ inline int64_t words(int64_t bits) { return (bits + 63) >> 6
 gf2_status set_error(gf2_status s, const char* fmt, ...);
 gf2_status hip_check(hipError_t e, const char* what);
 
+// Launch tracing: bracket a launch with events when tracing is on.
+class TraceScope {
+ public:
+  TraceScope(int kind, int items, double work, hipStream_t s);
+  ~TraceScope();
+ private:
+  int kind_, items_;
+  double work_;
+  hipStream_t s_;
+  hipEvent_t e0_ = nullptr;
+};
+bool trace_on();
+
 // ---- kernels (each .hip file owns its launches) ----
 // Products launched together with descriptors passed by value in the kernel arguments.
 constexpr int kMaxGroup = 49;   // 7^2 Strassen leaves

@@ -17,6 +17,8 @@
 //    (index in byte 1, lane offset in byte 0, buffer in byte 2); one ds_read_b128
 //    serves four rows per wave instruction (16 lanes x 16 B = one 256 B entry
 //    per row), the pattern that measured fastest on gfx950 LDS.
+#include <type_traits>
+
 #include "gf2_internal.h"
 
 namespace gf2 {
@@ -26,6 +28,9 @@ constexpr int KB = 8;                       // table width (kappa)
 constexpr int TILE_WORDS = 32;              // 2048 columns per tile
 constexpr int ENTRY_BYTES = TILE_WORDS * 8; // 256 B per table entry
 constexpr int TABLE_BYTES = (1 << KB) * ENTRY_BYTES;  // 64 KiB
+
+// Integer clamps (the generic min/max overloads of device code may go through double).
+__device__ __forceinline__ int64_t imin64(int64_t a, int64_t b) { return a < b ? a : b; }
 
 __device__ __forceinline__ uint4 xor4(uint4 a, uint4 b) {
   return make_uint4(a.x ^ b.x, a.y ^ b.y, a.z ^ b.z, a.w ^ b.w);
@@ -69,48 +74,47 @@ struct Tile {
   static constexpr int S = RW / 4;          // row slots per lane (4 rows per wave instruction)
   static constexpr int BM = WAVES * RW;
   static constexpr int WB = WAVES == 16 ? 4 : WAVES == 8 ? 3 : WAVES == 4 ? 2 : 1;
-  static constexpr int LOWB = KB - WB - 2;  // entry bits walked along the Gray code by one lane
   static_assert((1 << WB) == WAVES, "WAVES must be 2, 4, 8 or 16");
   static_assert(RW % 8 == 0, "RW must be a multiple of 8");
 };
 
-// Build this lane's entries of one stripe's table into LDS buffer ``buf``.
-// Entry x (bit b <-> B row kp+b) = (w << (LOWB+2)) | (q << LOWB) | g(i), g the binary
-// reflected Gray code: consecutive i differ in exactly bit ctz(i), so each further
-// entry is the previous one plus one row of B (Section 3.1).
-// ``rb`` covers the stripe's rows of B from the tile's first word; rows past k and
-// words past the last valid word of the last row read as zero.
-template <int WAVES, int RW>
-__device__ __forceinline__ void build_table(char* tab, int buf, int w, int q, int l16, const uint64_t* pb,
-                                            int64_t ldb, int rows, int64_t row_bytes, int lane_off) {
-  using T = Tile<WAVES, RW>;
-  // One resource per row of the stripe: the row offset lives in the (uniform) base,
-  // rows past k get an empty range, so every lane uses the same small offset.
-  auto row = [&](int b) -> uint4 {
+// Rows of B for one stripe, one dword per lane: lane j holds columns 32j..32j+31 of
+// the tile for each of the KB rows (rows past k and words past the row read as zero).
+struct StripeRows {
+  uint32_t r[KB];
+};
+
+template <int WAVES>
+__device__ __forceinline__ void load_stripe(StripeRows& sr, const uint64_t* pb, int64_t ldb, int rows,
+                                            int64_t row_bytes, int w, int lane) {
+  constexpr int HIB = KB - (WAVES == 16 ? 4 : WAVES == 8 ? 3 : WAVES == 4 ? 2 : 1);  // walked rows
+#pragma unroll
+  for (int b = 0; b < KB; ++b) {
+    // Rows selecting the wave's fixed high bits are only needed when that bit of w is set.
+    if (b >= HIB && !((w >> (b - HIB)) & 1)) { sr.r[b] = 0; continue; }
     const __amdgpu_buffer_rsrc_t r = make_rsrc(pb + b * ldb, b < rows ? row_bytes : 0);
-    const uint2 lo = bload2(r, lane_off), hi = bload2(r, lane_off + 8);
-    return make_uint4(lo.x, lo.y, hi.x, hi.y);
-  };
-  uint4 v = make_uint4(0, 0, 0, 0);
-#pragma unroll
-  for (int b = T::LOWB + 2; b < KB; ++b)         // high bits: wave-uniform choice of rows
-    if ((w >> (b - T::LOWB - 2)) & 1) v = xor4(v, row(b));
-#pragma unroll
-  for (int b = T::LOWB; b < T::LOWB + 2; ++b) {  // middle bits: chosen per quarter-wave
-    const uint4 r = row(b);
-    if ((q >> (b - T::LOWB)) & 1) v = xor4(v, r);
+    sr.r[b] = bload1(r, lane * 4);
   }
-  uint4 low[T::LOWB > 0 ? T::LOWB : 1];
+}
+
+// Build this wave's share of one stripe's table into LDS buffer ``buf``: the entries
+// x = (w << HIB) | g(i), i < 2^HIB, g the binary reflected Gray code.  Bit b of x selects
+// B row kp+b, so T[x] = XOR of the selected rows; consecutive Gray codes differ in
+// exactly bit ctz(i), hence each further entry costs one row addition (Section 3.1).
+// One wave instruction writes one whole 256 B entry (lane j = dword j).
+template <int WAVES>
+__device__ __forceinline__ void build_table(char* tab, int buf, int w, int lane, const StripeRows& sr) {
+  constexpr int HIB = KB - (WAVES == 16 ? 4 : WAVES == 8 ? 3 : WAVES == 4 ? 2 : 1);
+  uint32_t v = 0;
 #pragma unroll
-  for (int b = 0; b < T::LOWB; ++b) low[b] = row(b);
-  const uint32_t base = ((uint32_t)w << (T::LOWB + 2)) | ((uint32_t)q << T::LOWB);
-  char* dst = tab + ((uint32_t)buf << 16) + l16 * 16;
-  *reinterpret_cast<uint4*>(dst + base * ENTRY_BYTES) = v;
+  for (int b = HIB; b < KB; ++b) v ^= sr.r[b];       // zero where w's bit is clear
+  char* dst = tab + ((uint32_t)buf << 16) + lane * 4;
+  const uint32_t base = (uint32_t)w << HIB;
+  *reinterpret_cast<uint32_t*>(dst + base * ENTRY_BYTES) = v;
 #pragma unroll
-  for (int i = 1; i < (1 << T::LOWB); ++i) {
-    v = xor4(v, low[__builtin_ctz(i)]);
-    const uint32_t x = base | (uint32_t)(i ^ (i >> 1));
-    *reinterpret_cast<uint4*>(dst + x * ENTRY_BYTES) = v;
+  for (int i = 1; i < (1 << HIB); ++i) {
+    v ^= sr.r[__builtin_ctz(i)];
+    *reinterpret_cast<uint32_t*>(dst + (base | (uint32_t)(i ^ (i >> 1))) * ENTRY_BYTES) = v;
   }
 }
 
@@ -128,58 +132,79 @@ __device__ __forceinline__ void m4rm_tile(const MulDesc& d, int tm, int tn, char
   const int64_t c0 = (int64_t)tn * TILE_WORDS;          // tile's first word column (uniform)
   const int64_t Wt = Wn - c0;                           // valid words from the tile start
   const int64_t row0 = (int64_t)tm * T::BM + (int64_t)w * RW;   // first row of this wave (uniform)
-  const int rows_here = (int)min<int64_t>(d.m - row0, RW);
+  const int rows_here = (int)imin64(d.m - row0, RW);
   const int nstripes = (d.k + KB - 1) / KB;
-  const int lda_b = (int)(d.lda * 8);
   const int kdw = (d.k + 31) >> 5;                      // A dwords per row that hold bits < k
-  // A: this wave's rows; offsets past the last existing row read as zero.
+  const uint32_t lanebase = (uint32_t)l16 * 16u;
+
+  // A indices: dword g of a row holds the 8-bit indices of stripes 4g..4g+3.  Each lane
+  // keeps the dwords of its own row slots for the current group and prefetches the next
+  // group's; offsets past the wave's last existing row read as zero.
+  const int lda_b = (int)(d.lda * 8);
   const __amdgpu_buffer_rsrc_t ra =
       make_rsrc(d.A + row0 * d.lda, rows_here > 0 ? (int64_t)(rows_here - 1) * lda_b + 4 * kdw : 0);
-  const uint32_t lanebase = (uint32_t)l16 * 16u;
 
   uint4 acc[S];
 #pragma unroll
   for (int s = 0; s < S; ++s) acc[s] = make_uint4(0, 0, 0, 0);
-
-  uint32_t aw[S], an[S];
+  // Two register sets of A dwords swap roles every group (current / prefetched), so
+  // the prefetch needs no copies and is waited for only when it is used.
+  uint32_t ax[S], ay[S];
   auto load_a = [&](int g, uint32_t (&dst)[S]) {
 #pragma unroll
     for (int s = 0; s < S; ++s) dst[s] = bload1(ra, (4 * s + q) * lda_b + 4 * g);
   };
-  if (nstripes > 0) load_a(0, an);
 
-  auto build = [&](int p, int buf) {
+  // B rows of stripe p+1 are loaded before the lookups of stripe p, so their latency
+  // is hidden behind the lookups; the table is built from them afterwards.
+  StripeRows sr;
+  auto fetch = [&](int p) {
     const int64_t kp = (int64_t)p * KB;
-    const int rows = (int)min<int64_t>(d.k - kp, KB);
-    build_table<WAVES, RW>(tab, buf, w, q, l16, d.B + kp * d.ldb + c0, d.ldb, rows, 8 * Wt, lw * 8);
+    load_stripe<WAVES>(sr, d.B + kp * d.ldb + c0, d.ldb, (int)imin64(d.k - kp, KB), 8 * Wt, w, L);
   };
-  if (nstripes > 0) build(0, 0);
+  if (nstripes > 0) {
+    load_a(0, ax);
+    fetch(0);
+    build_table<WAVES>(tab, 0, w, L, sr);
+  }
   __syncthreads();
 
-  for (int p = 0; p < nstripes; ++p) {
-    if ((p & 3) == 0) {
+  // One stripe: lookups of stripe p in table buffer p&1 with byte U of the A dwords,
+  // then the table of stripe p+1 into the other buffer.
+  auto stripe = [&](int p, auto U, const uint32_t (&aw)[S]) {
+    if (p + 1 < nstripes) fetch(p + 1);
+    const uint32_t lb = lanebase | ((uint32_t)(p & 1) << 16);
+    constexpr uint32_t sel = 0x0c020400u + ((uint32_t)decltype(U)::value << 8);  // byte0 <- lb, byte1 <- A byte U, byte2 <- lb
+    constexpr int INFL = WAVES >= 16 ? 2 : 4;          // lookups in flight per wave
 #pragma unroll
-      for (int s = 0; s < S; ++s) aw[s] = an[s];
-      if (p + 4 < nstripes) load_a((p >> 2) + 1, an);
-    }
-    const int buf = p & 1;
-    const uint32_t lb = lanebase | ((uint32_t)buf << 16);
-    const uint32_t sel = 0x0c020400u + ((uint32_t)(p & 3) << 8);  // byte0 <- lb, byte1 <- A byte, byte2 <- lb
+    for (int s0 = 0; s0 < S; s0 += INFL) {
 #pragma unroll
-    for (int s0 = 0; s0 < S; s0 += 4) {
-#pragma unroll
-      for (int s = s0; s < s0 + 4 && s < S; ++s) {
+      for (int s = s0; s < s0 + INFL && s < S; ++s) {
         const uint32_t addr = __builtin_amdgcn_perm(aw[s], lb, sel);
         acc[s] = xor4(acc[s], *reinterpret_cast<const uint4*>(tab + addr));
       }
-      // Register fence: the XORs of this group complete here, so at most four
+      // Register fence: the XORs of this group complete here, so at most INFL
       // lookups are in flight and none is held across the table build.
 #pragma unroll
-      for (int s = s0; s < s0 + 4 && s < S; ++s)
+      for (int s = s0; s < s0 + INFL && s < S; ++s)
         asm volatile("" : "+v"(acc[s].x), "+v"(acc[s].y), "+v"(acc[s].z), "+v"(acc[s].w));
     }
-    if (p + 1 < nstripes) build(p + 1, buf ^ 1);
+    if (p + 1 < nstripes) build_table<WAVES>(tab, (p & 1) ^ 1, w, L, sr);
     __syncthreads();
+  };
+  // A group: four stripes sharing one set of A dwords; the next group's set is loaded first.
+  auto group = [&](int g, const uint32_t (&cur)[S], uint32_t (&nxt)[S]) {
+    const int p0 = 4 * g;
+    if (p0 + 4 < nstripes) load_a(g + 1, nxt);
+    stripe(p0, std::integral_constant<int, 0>{}, cur);
+    if (p0 + 1 < nstripes) stripe(p0 + 1, std::integral_constant<int, 1>{}, cur);
+    if (p0 + 2 < nstripes) stripe(p0 + 2, std::integral_constant<int, 2>{}, cur);
+    if (p0 + 3 < nstripes) stripe(p0 + 3, std::integral_constant<int, 3>{}, cur);
+  };
+  const int ngroups = (nstripes + 3) >> 2;
+  for (int g = 0; g < ngroups; g += 2) {
+    group(g, ax, ay);
+    if (g + 1 < ngroups) group(g + 1, ay, ax);
   }
 
   // Store: rows < m, words < Wn; padding bits of the last word are cleared.
@@ -288,6 +313,9 @@ gf2_status m4rm_launch_group(const MulDesc* descs, int count, int variant, hipSt
     }
     if (g.count == 0) continue;
     g.tile_start[g.count] = (int)total;
+    double work = 0;
+    for (int i = 0; i < g.count; ++i) work += (double)g.d[i].m * ((g.d[i].k + KB - 1) / KB) * (double)words(g.d[i].n);
+    TraceScope trace(GF2_TRACE_M4RM, g.count, work, s);
     hipLaunchKernelGGL(v.group, dim3((unsigned)total), dim3(v.waves * 64), 0, s, g);
     gf2_status st = hip_check(hipGetLastError(), "m4rm_group launch");
     if (st != GF2_OK) return st;

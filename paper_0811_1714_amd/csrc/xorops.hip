@@ -109,6 +109,7 @@ unsigned grid_for(int64_t total) {
 
 gf2_status fill_zero(const OView& o, hipStream_t s) {
   if (o.rows <= 0 || o.wds <= 0) return GF2_OK;
+  TraceScope trace(GF2_TRACE_FILL, 1, 8.0 * o.rows * o.wds, s);
   hipLaunchKernelGGL(fill_zero_kernel, dim3(grid_for(o.rows * o.wds)), dim3(kThreads), 0, s, o);
   return hip_check(hipGetLastError(), "fill_zero launch");
 }
@@ -119,6 +120,7 @@ gf2_status strassen_pre(int kind, const QView in[4], uint64_t* const out[4], int
   PreArgs a;
   for (int i = 0; i < 4; ++i) { a.in[i] = in[i]; a.out[i] = out[i]; }
   a.ldo = ldo; a.R = R; a.Wd = Wd;
+  TraceScope trace(GF2_TRACE_PRE, 1, 8.0 * 8 * R * Wd, s);   // 4 quadrants in, 4 out
   if (kind == 0) hipLaunchKernelGGL(strassen_pre_kernel<0>, dim3(grid_for(R * Wd)), dim3(kThreads), 0, s, a);
   else hipLaunchKernelGGL(strassen_pre_kernel<1>, dim3(grid_for(R * Wd)), dim3(kThreads), 0, s, a);
   return hip_check(hipGetLastError(), "strassen_pre launch");
@@ -132,6 +134,7 @@ gf2_status strassen_post(const uint64_t* const P[7], int64_t ldp, const OView c[
   a.mode = out_mode;
   const int64_t total = c[0].rows * c[0].wds;
   if (total <= 0) return GF2_OK;
+  TraceScope trace(GF2_TRACE_POST, 1, 8.0 * 11 * total, s);   // 7 products in, 4 quadrants out
   hipLaunchKernelGGL(strassen_post_kernel, dim3(grid_for(total)), dim3(kThreads), 0, s, a);
   return hip_check(hipGetLastError(), "strassen_post launch");
 }
