@@ -40,13 +40,48 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--sweep", action="store_true", help="time candidate schedules for n = 8K, 16K, 32K")
     ap.add_argument("--sweep-n", type=int, nargs="*", default=None)
+    ap.add_argument("--sweep-variants", type=int, nargs="*", default=None)
     ap.add_argument("--check-rows", type=int, default=16, help="rows compared with the oracle after timing")
+    ap.add_argument("--copy-calibration", action="store_true", help="run a plain 1 GiB device copy (counter scale)")
     return ap.parse_args()
 
 
 def default_schedule(g, n):
-    """Schedule used for the headline: tuned on MI355X."""
-    return g.Schedule(g.KERNEL_M4RM, 0, 0, 1)
+    """Headline schedule, from the MI355X sweep: two Strassen-Winograd levels
+    (cutoff n/4) over the two-table M4RM tile of 1536 rows."""
+    return g.Schedule(g.KERNEL_M4RM, 0, n // 4 if n >= 8192 else 0, 1)
+
+
+def m4rm_source_hash():
+    import hashlib
+    src = os.path.join(ROOT, "paper_0811_1714_amd", "csrc", "m4rm.hip")
+    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+
+
+def traffic_from_profile(n, sched):
+    """HBM bytes per M4RM launch from the committed rocprofv3 counter summary, or None when
+    the summary is for another kernel source, workload or schedule."""
+    path = os.path.join(ROOT, "profiles", "m4rm_traffic.json")
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if (rec.get("m4rm_source_sha256_16") != m4rm_source_hash() or rec.get("n") != n
+            or rec.get("variant") != sched.variant or rec.get("cutoff") != sched.cutoff):
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def copy_calibration():
+    """A plain device copy of known size, for scaling the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    nbytes = 1 << 30
+    src = torch.ones(nbytes // 8, dtype=torch.int64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes, "launches": 3}), flush=True)
 
 
 def to_dev(a):
@@ -72,6 +107,7 @@ def time_product(g, dA, dB, dC, n, sched, steps, warmup):
 
 
 SWEEP_N = (8192, 16384, 32768)
+SWEEP_VARIANTS = None
 
 
 def sweep(g):
@@ -85,7 +121,7 @@ def sweep(g):
         for cutoff in (0, n // 2, n // 4):
             if cutoff and cutoff < 2048 or (cutoff == n // 2 and n > 8192):
                 continue
-            for v in range(g.kernel_variants(g.KERNEL_M4RM)):
+            for v in SWEEP_VARIANTS or range(g.kernel_variants(g.KERNEL_M4RM)):
                 s = g.Schedule(g.KERNEL_M4RM, v, cutoff, 1)
                 ms, per = time_product(g, dA, dB, dC, n, s, 3, 1)
                 print(json.dumps({"n": n, "variant": v, "cutoff": cutoff, "ms": round(min(per), 4),
@@ -122,10 +158,14 @@ def main():
     import oracle
 
     g.lib()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.sweep:
-        global SWEEP_N
+        global SWEEP_N, SWEEP_VARIANTS
         if args.sweep_n:
             SWEEP_N = tuple(args.sweep_n)
+        SWEEP_VARIANTS = args.sweep_variants
         sweep(g)
         return
     n = args.n
@@ -181,7 +221,7 @@ def main():
                                         "splitk": sched.splitk},
                    "ms_min": min(per), "ms_median": float(np.median(per)), "bit_exact_sampled_rows": exact},
         "roofline": {"bound": "lds", "kernel": "m4rm leaves", "achieved": achieved / 1e9, "peak": LDS_PEAK / 1e9,
-                     "unit": "GB/s", "frac": achieved / LDS_PEAK, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / LDS_PEAK, "traffic": traffic_from_profile(n, sched),
                      "launches_per_step": launches / max(1, args.steps), "kernel_ms": kms,
                      "word_xors_per_launch": work,
                      "valu_roof_frac": (work / VALU_WORD_XOR_PEAK) / (kms * 1e-3)},

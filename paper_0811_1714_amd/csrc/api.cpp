@@ -119,24 +119,32 @@ gf2_schedule g_override{};
 
 uint64_t tail_of(int64_t cols) { return (cols & 63) ? ((1ull << (cols & 63)) - 1) : ~0ull; }
 
-// Default schedule for a shape: M4RM with a tile height that still fills the chip,
-// k split when there are too few C tiles for 256 compute units.
+// Default schedule for a shape (the fixed heuristic, used when nothing better is known):
+// the tallest M4RM tile that still gives every compute unit work, two Strassen-Winograd
+// levels once the smallest dimension reaches 8192, and k split when there are too few
+// C tiles to fill 256 compute units.
+int64_t tiles_for(int64_t m, int64_t n, int v) {
+  const int64_t bm = m4rm_tile_rows(v), tw = m4rm_tile_words(v);
+  return ((m + bm - 1) / bm) * ((words(n) + tw - 1) / tw);
+}
+
 gf2_schedule default_schedule(int64_t m, int64_t k, int64_t n) {
   gf2_schedule s{};
   s.kernel = GF2_KERNEL_M4RM;
-  s.cutoff = 0;
-  const int64_t tn = (words(n) + 31) / 32;
-  int v = 0;
-  const int order[] = {0, 2, 3, 4};
+  const int64_t mn = m < n ? (m < k ? m : k) : (n < k ? n : k);
+  s.cutoff = mn >= 8192 ? (int32_t)(mn / 4) : 0;
+  const int64_t lm = s.cutoff ? (m + 3) / 4 : m, ln = s.cutoff ? (n + 3) / 4 : n;
+  const int64_t leaves = s.cutoff ? 49 : 1;
+  const int order[] = {0, 1, 2, 3};
+  int v = 3;
   for (int vi : order) {
-    v = vi;
-    const int64_t tm = (m + m4rm_tile_rows(vi) - 1) / m4rm_tile_rows(vi);
-    if (tm * tn >= 512) break;
+    if (tiles_for(lm, ln, vi) * leaves >= 512) { v = vi; break; }
   }
   s.variant = v;
-  const int64_t tiles = ((m + m4rm_tile_rows(v) - 1) / m4rm_tile_rows(v)) * tn;
+  const int64_t tiles = tiles_for(lm, ln, v) * leaves;
   int sk = 1;
-  while (tiles * sk < 512 && k / (64 * (sk * 2)) >= 16 && sk < kMaxGroup) sk *= 2;
+  if (!s.cutoff)
+    while (tiles * sk < 512 && k / (64 * (sk * 2)) >= 16 && sk * 2 <= kMaxGroup) sk *= 2;
   s.splitk = sk;
   return s;
 }

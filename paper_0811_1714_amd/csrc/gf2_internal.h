@@ -57,6 +57,7 @@ struct GroupArgs {
 // M4RM base case (m4rm.hip).
 int m4rm_num_variants();
 int m4rm_tile_rows(int variant);
+int m4rm_tile_words(int variant);
 int64_t m4rm_tiles(const MulDesc& d, int variant);
 gf2_status m4rm_launch_group(const MulDesc* descs, int count, int variant, hipStream_t s);
 gf2_status m4rm_launch_list(const MulDesc* dev_descs, const int* dev_tile_start, int count, int64_t total_tiles,

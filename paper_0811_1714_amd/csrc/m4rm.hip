@@ -238,22 +238,171 @@ __device__ __forceinline__ void m4rm_tile_any(const MulDesc& d, int tm, int tn, 
 // Up to kMaxGroup products in one launch, descriptors passed by value (no device
 // staging, so the launch can be captured into a graph as is).  Workgroup b belongs to
 // the product i with tile_start[i] <= b < tile_start[i+1].
+// ---------------------------------------------------------------------------
+// Two tables per phase (Algorithm 3 with t = 2).  The tile is 1024 columns wide,
+// so the pair of 8-bit tables of a 16-row phase of B fits one 64 KiB buffer,
+// interleaved: entry x of table h (h = 0, 1) at x*256 + h*128, column dword j at
+// +4j.  One ds_write_b32 wave instruction writes entry x of both tables (lanes
+// 0-31 walk the Gray code over rows kp..kp+7, lanes 32-63 over kp+8..kp+15), and
+// one v_bitop3 folds both lookups of a row into its accumulator
+// ("AddTwoRowsFromTable").  Eight rows per lookup instruction (8 lanes x 16 B per
+// 128 B half-entry).  Halving the tile width doubles the rows that share each table.
+constexpr int T2_WORDS = 16;                // 1024 columns per tile
+constexpr int PB = 2 * KB;                  // rows of B per phase
+
+template <int WAVES, int S>
+struct Tile2 {
+  static constexpr int RW = 8 * S;          // rows per wave: eight per lookup instruction
+  static constexpr int BM = WAVES * RW;
+  static constexpr int HIB = KB - (WAVES == 16 ? 4 : WAVES == 8 ? 3 : WAVES == 4 ? 2 : 1);
+};
+
+__device__ __forceinline__ uint4 xor3v(uint4 a, uint4 b, uint4 c) {
+  return make_uint4(__builtin_amdgcn_bitop3_b32(a.x, b.x, c.x, 0x96), __builtin_amdgcn_bitop3_b32(a.y, b.y, c.y, 0x96),
+                    __builtin_amdgcn_bitop3_b32(a.z, b.z, c.z, 0x96), __builtin_amdgcn_bitop3_b32(a.w, b.w, c.w, 0x96));
+}
+
+template <int WAVES, int S, int INFL, bool EDGE>
+__device__ __forceinline__ void m4rm2_tile(const MulDesc& d, int tm, int tn, char* tab) {
+  using T = Tile2<WAVES, S>;
+  const int tid = threadIdx.x;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int L = tid & 63, g8 = L >> 3, l8 = L & 7;
+  const int64_t Wn = words(d.n);
+  const int lw = 2 * l8;                                // lane's word offset inside the tile
+  const int64_t c0 = (int64_t)tn * T2_WORDS;            // tile's first word column (uniform)
+  const int64_t Wt = Wn - c0;                           // valid words from the tile start
+  const int64_t row0 = (int64_t)tm * T::BM + (int64_t)w * T::RW;
+  const int rows_here = (int)imin64(d.m - row0, T::RW);
+  const int nphases = (d.k + PB - 1) / PB;
+  const int kdw = (d.k + 31) >> 5;
+  const int lda_b = (int)(d.lda * 8), ldb_b = (int)(d.ldb * 8);
+  // A: dword gd of a row holds the indices of phases 2gd (bytes 0, 1) and 2gd+1 (bytes 2, 3).
+  const __amdgpu_buffer_rsrc_t ra =
+      make_rsrc(d.A + row0 * d.lda, rows_here > 0 ? (int64_t)(rows_here - 1) * lda_b + 4 * kdw : 0);
+  const uint32_t lb0 = (uint32_t)l8 * 16u, lb1 = 128u + (uint32_t)l8 * 16u;
+  // B: lane L builds column dword L&31 of table L>>5, i.e. rows kp + 8*(L>>5) + b.
+  const int boff = (L >> 5) * KB * ldb_b + (L & 31) * 4;
+
+  uint4 acc[S];
+#pragma unroll
+  for (int s = 0; s < S; ++s) acc[s] = make_uint4(0, 0, 0, 0);
+  uint32_t ax[S], ay[S];
+  auto load_a = [&](int gd, uint32_t (&dst)[S]) {
+#pragma unroll
+    for (int s = 0; s < S; ++s) dst[s] = bload1(ra, (8 * s + g8) * lda_b + 4 * gd);
+  };
+  StripeRows sr;
+  auto fetch = [&](int p) {
+    constexpr int HIB = T::HIB;
+    const int64_t kp = (int64_t)p * PB;
+    const int rows = (int)imin64(d.k - kp, PB);
+    const __amdgpu_buffer_rsrc_t rb = make_rsrc(d.B + kp * d.ldb + c0, (int64_t)(rows - 1) * ldb_b + 8 * Wt);
+#pragma unroll
+    for (int b = 0; b < KB; ++b) {
+      if (b >= HIB && !((w >> (b - HIB)) & 1)) { sr.r[b] = 0; continue; }
+      sr.r[b] = bload1(rb, boff + b * ldb_b);
+    }
+  };
+  if (nphases > 0) {
+    load_a(0, ax);
+    fetch(0);
+    build_table<WAVES>(tab, 0, w, L, sr);
+  }
+  __syncthreads();
+
+  auto phase = [&](int p, auto U, const uint32_t (&aw)[S]) {
+    if (p + 1 < nphases) fetch(p + 1);
+    const uint32_t buf = (uint32_t)(p & 1) << 16;
+    constexpr uint32_t sel0 = 0x0c020400u + ((uint32_t)(2 * decltype(U)::value) << 8);
+    constexpr uint32_t sel1 = 0x0c020400u + ((uint32_t)(2 * decltype(U)::value + 1) << 8);
+#pragma unroll
+    for (int s0 = 0; s0 < S; s0 += INFL) {
+#pragma unroll
+      for (int s = s0; s < s0 + INFL && s < S; ++s) {
+        const uint4 t0 = *reinterpret_cast<const uint4*>(tab + __builtin_amdgcn_perm(aw[s], lb0 | buf, sel0));
+        const uint4 t1 = *reinterpret_cast<const uint4*>(tab + __builtin_amdgcn_perm(aw[s], lb1 | buf, sel1));
+        acc[s] = xor3v(acc[s], t0, t1);
+      }
+#pragma unroll
+      for (int s = s0; s < s0 + INFL && s < S; ++s)
+        asm volatile("" : "+v"(acc[s].x), "+v"(acc[s].y), "+v"(acc[s].z), "+v"(acc[s].w));
+    }
+    if (p + 1 < nphases) build_table<WAVES>(tab, (p & 1) ^ 1, w, L, sr);
+    __syncthreads();
+  };
+  auto group = [&](int gd, const uint32_t (&cur)[S], uint32_t (&nxt)[S]) {
+    const int p0 = 2 * gd;
+    if (p0 + 2 < nphases) load_a(gd + 1, nxt);
+    phase(p0, std::integral_constant<int, 0>{}, cur);
+    if (p0 + 1 < nphases) phase(p0 + 1, std::integral_constant<int, 1>{}, cur);
+  };
+  const int ngroups = (nphases + 1) >> 1;
+  for (int gd = 0; gd < ngroups; gd += 2) {
+    group(gd, ax, ay);
+    if (gd + 1 < ngroups) group(gd + 1, ay, ax);
+  }
+
+  const uint64_t tail = (d.n & 63) ? ((1ull << (d.n & 63)) - 1) : ~0ull;
+  const uint64_t m0 = (EDGE && lw == Wt - 1) ? tail : ~0ull;
+  const uint64_t m1 = (EDGE && lw + 1 == Wt - 1) ? tail : ~0ull;
+  uint64_t* pc = d.C + row0 * d.ldc + c0 + lw;
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const int rr = 8 * s + g8;
+    if (!EDGE || rr < rows_here) {
+      uint64_t* cp = pc + (int64_t)rr * d.ldc;
+      const uint64_t w0 = ((uint64_t)acc[s].x | ((uint64_t)acc[s].y << 32)) & m0;
+      const uint64_t w1 = ((uint64_t)acc[s].z | ((uint64_t)acc[s].w << 32)) & m1;
+      if (!EDGE || lw < Wt) store_word(cp, w0, d.out);
+      if (!EDGE || lw + 1 < Wt) store_word(cp + 1, w1, d.out);
+    }
+  }
+}
+
+template <int WAVES, int S, int INFL>
+__device__ __forceinline__ void m4rm2_tile_any(const MulDesc& d, int tm, int tn, char* tab) {
+  using T = Tile2<WAVES, S>;
+  const int64_t Wn = words(d.n);
+  const bool edge = (int64_t)(tm + 1) * T::BM > d.m || (int64_t)(tn + 1) * T2_WORDS > Wn ||
+                    ((d.n & 63) != 0 && (int64_t)(tn + 1) * T2_WORDS == Wn);
+  if (edge) m4rm2_tile<WAVES, S, INFL, true>(d, tm, tn, tab);
+  else m4rm2_tile<WAVES, S, INFL, false>(d, tm, tn, tab);
+}
+
+// Tile policies: one table per stripe (T1: 2048 columns) or two per phase (T2: 1024).
 template <int WAVES, int RW>
-__global__ __launch_bounds__(WAVES * 64) void m4rm_group(GroupArgs g) {
+struct PolicyT1 {
+  static constexpr int BM = WAVES * RW, TW = TILE_WORDS, NT = WAVES * 64;
+  __device__ static void run(const MulDesc& d, int tm, int tn, char* tab) { m4rm_tile_any<WAVES, RW>(d, tm, tn, tab); }
+};
+template <int WAVES, int S, int INFL>
+struct PolicyT2 {
+  static constexpr int BM = Tile2<WAVES, S>::BM, TW = T2_WORDS, NT = WAVES * 64;
+  __device__ static void run(const MulDesc& d, int tm, int tn, char* tab) {
+    m4rm2_tile_any<WAVES, S, INFL>(d, tm, tn, tab);
+  }
+};
+
+// Up to kMaxGroup products in one launch, descriptors passed by value (no device
+// staging, so the launch can be captured into a graph as is).  Workgroup b belongs to
+// the product i with tile_start[i] <= b < tile_start[i+1].
+template <class P>
+__global__ __launch_bounds__(P::NT) void m4rm_group(GroupArgs g) {
   __shared__ uint4 tab[2 * TABLE_BYTES / 16];
   const int t = xcd_remap(blockIdx.x, gridDim.x);
   int i = 0;
   while (i + 1 < g.count && g.tile_start[i + 1] <= t) ++i;
   const MulDesc& d = g.d[i];
   const int local = t - g.tile_start[i];
-  const int tiles_m = (d.m + Tile<WAVES, RW>::BM - 1) / Tile<WAVES, RW>::BM;
-  m4rm_tile_any<WAVES, RW>(d, local % tiles_m, local / tiles_m, reinterpret_cast<char*>(tab));
+  const int tiles_m = (d.m + P::BM - 1) / P::BM;
+  P::run(d, local % tiles_m, local / tiles_m, reinterpret_cast<char*>(tab));
 }
 
 // Descriptor list in device memory (batched products).
-template <int WAVES, int RW>
-__global__ __launch_bounds__(WAVES * 64) void m4rm_list(const MulDesc* __restrict__ ds,
-                                                        const int* __restrict__ tile_start, int count) {
+template <class P>
+__global__ __launch_bounds__(P::NT) void m4rm_list(const MulDesc* __restrict__ ds, const int* __restrict__ tile_start,
+                                                   int count) {
   __shared__ uint4 tab[2 * TABLE_BYTES / 16];
   const int t = xcd_remap(blockIdx.x, gridDim.x);
   int lo = 0, hi = count - 1;
@@ -263,25 +412,29 @@ __global__ __launch_bounds__(WAVES * 64) void m4rm_list(const MulDesc* __restric
   }
   const MulDesc d = ds[lo];
   const int local = t - tile_start[lo];
-  const int tiles_m = (d.m + Tile<WAVES, RW>::BM - 1) / Tile<WAVES, RW>::BM;
-  m4rm_tile_any<WAVES, RW>(d, local % tiles_m, local / tiles_m, reinterpret_cast<char*>(tab));
+  const int tiles_m = (d.m + P::BM - 1) / P::BM;
+  P::run(d, local % tiles_m, local / tiles_m, reinterpret_cast<char*>(tab));
 }
 
 struct Variant {
-  int waves, rw;
+  int threads, bm, tw;      // workgroup size, tile rows, tile width in words
   void (*group)(GroupArgs);
   void (*list)(const MulDesc*, const int*, int);
 };
 
-#define GF2_M4RM_VARIANT(W, R) { W, R, m4rm_group<W, R>, m4rm_list<W, R> }
-const Variant kVariants[] = {
-    GF2_M4RM_VARIANT(16, 48),   // 0: BM 768, 16 waves
-    GF2_M4RM_VARIANT(8, 96),    // 1: BM 768, 8 waves
-    GF2_M4RM_VARIANT(16, 32),   // 2: BM 512
-    GF2_M4RM_VARIANT(8, 32),    // 3: BM 256
-    GF2_M4RM_VARIANT(4, 32),    // 4: BM 128
-};
-#undef GF2_M4RM_VARIANT
+using V0 = PolicyT2<16, 12, 2>;   // t=2, BM 1536 x 1024 columns, 16 waves
+using V1 = PolicyT2<16, 8, 4>;    // t=2, BM 1024
+using V2 = PolicyT2<16, 4, 4>;    // t=2, BM 512
+using V3 = PolicyT2<8, 4, 4>;     // t=2, BM 256
+using V4 = PolicyT1<16, 48>;      // t=1, BM 768 x 2048 columns, 16 waves
+using V5 = PolicyT2<8, 24, 4>;    // t=2, BM 1536, 8 waves
+using V6 = PolicyT2<8, 16, 4>;    // t=2, BM 1024, 8 waves
+using V7 = PolicyT2<16, 8, 2>;    // t=2, BM 1024, two lookups in flight
+using V8 = PolicyT2<8, 24, 6>;    // t=2, BM 1536, 8 waves, six in flight
+#define GF2_V(P) { P::NT, P::BM, P::TW, m4rm_group<P>, m4rm_list<P> }
+const Variant kVariants[] = {GF2_V(V0), GF2_V(V1), GF2_V(V2), GF2_V(V3), GF2_V(V4),
+                             GF2_V(V5), GF2_V(V6), GF2_V(V7), GF2_V(V8)};
+#undef GF2_V
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
 const Variant& variant_of(int v) { return kVariants[(v < 0 || v >= kNumVariants) ? 0 : v]; }
@@ -289,11 +442,12 @@ const Variant& variant_of(int v) { return kVariants[(v < 0 || v >= kNumVariants)
 }  // namespace
 
 int m4rm_num_variants() { return kNumVariants; }
-int m4rm_tile_rows(int variant) { return variant_of(variant).waves * variant_of(variant).rw; }
+int m4rm_tile_rows(int variant) { return variant_of(variant).bm; }
+int m4rm_tile_words(int variant) { return variant_of(variant).tw; }
 
 int64_t m4rm_tiles(const MulDesc& d, int variant) {
-  const int64_t bm = m4rm_tile_rows(variant);
-  return ((d.m + bm - 1) / bm) * ((words(d.n) + TILE_WORDS - 1) / TILE_WORDS);
+  const int64_t bm = variant_of(variant).bm, tw = variant_of(variant).tw;
+  return ((d.m + bm - 1) / bm) * ((words(d.n) + tw - 1) / tw);
 }
 
 gf2_status m4rm_launch_group(const MulDesc* descs, int count, int variant, hipStream_t s) {
@@ -316,7 +470,7 @@ gf2_status m4rm_launch_group(const MulDesc* descs, int count, int variant, hipSt
     double work = 0;
     for (int i = 0; i < g.count; ++i) work += (double)g.d[i].m * ((g.d[i].k + KB - 1) / KB) * (double)words(g.d[i].n);
     TraceScope trace(GF2_TRACE_M4RM, g.count, work, s);
-    hipLaunchKernelGGL(v.group, dim3((unsigned)total), dim3(v.waves * 64), 0, s, g);
+    hipLaunchKernelGGL(v.group, dim3((unsigned)total), dim3(v.threads), 0, s, g);
     gf2_status st = hip_check(hipGetLastError(), "m4rm_group launch");
     if (st != GF2_OK) return st;
   }
@@ -328,7 +482,7 @@ gf2_status m4rm_launch_list(const MulDesc* dev_descs, const int* dev_tile_start,
   if (total_tiles == 0 || count == 0) return GF2_OK;
   if (total_tiles > INT32_MAX) return set_error(GF2_ERR_UNSUPPORTED, "m4rm: too many tiles");
   const Variant& v = variant_of(variant);
-  hipLaunchKernelGGL(v.list, dim3((unsigned)total_tiles), dim3(v.waves * 64), 0, s, dev_descs, dev_tile_start, count);
+  hipLaunchKernelGGL(v.list, dim3((unsigned)total_tiles), dim3(v.threads), 0, s, dev_descs, dev_tile_start, count);
   return hip_check(hipGetLastError(), "m4rm_list launch");
 }
 
