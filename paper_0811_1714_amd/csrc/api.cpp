@@ -3,6 +3,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
+#include <algorithm>
 #include <cstring>
 #include <mutex>
 #include <vector>
@@ -227,10 +228,27 @@ MulDesc make_desc(const View& A, const View& B, uint64_t* C, int64_t ldc, int ou
   return d;
 }
 
+// Scratch the base kernel needs beyond the operands (the popcount kernel's B transpose,
+// reused leaf after leaf).
+size_t base_scratch_words(const gf2_schedule& s, const std::vector<MulDesc>& ds) {
+  size_t w = 0;
+  if (s.kernel == GF2_KERNEL_CUBIC)
+    for (const MulDesc& d : ds) w = std::max(w, cubic_scratch_words(d));
+  return w;
+}
+
 // Base-case products launched together.
-gf2_status run_base(const gf2_schedule& s, const std::vector<MulDesc>& ds, hipStream_t st) {
+gf2_status run_base(const gf2_schedule& s, const std::vector<MulDesc>& ds, uint64_t* scratch, hipStream_t st) {
   if (ds.empty()) return GF2_OK;
   switch (s.kernel) {
+    case GF2_KERNEL_MFMA:
+      return mfma_launch_group(ds.data(), (int)ds.size(), st);
+    case GF2_KERNEL_CUBIC:
+      for (const MulDesc& d : ds) {
+        gf2_status r = cubic_launch(d, scratch, st);
+        if (r != GF2_OK) return r;
+      }
+      return GF2_OK;
     case GF2_KERNEL_M4RM:
     default:
       return m4rm_launch_group(ds.data(), (int)ds.size(), s.variant, st);
@@ -335,44 +353,60 @@ void plan_splitk(std::vector<MulDesc>& out, const View& A, const View& B, uint64
   }
 }
 
+// Leaves of the product and the workspace they need: Strassen temporaries first, then
+// the base kernel's scratch.  ``base`` == nullptr sizes only.
+struct ProductPlan {
+  StrassenPlan st;
+  std::vector<MulDesc> leaves;   // when not recursing
+  size_t scratch_words = 0;
+  size_t total_words() const { return st.ws_words + scratch_words; }
+};
+
+void plan_product(ProductPlan& pp, uint64_t* base, uint64_t* C, int64_t ldc, const uint64_t* A, int64_t lda,
+                  const uint64_t* B, int64_t ldb, int64_t m, int64_t k, int64_t n, bool accumulate,
+                  const gf2_schedule& s) {
+  const int out = accumulate ? OUT_XOR : OUT_STORE;
+  const View Av{A, lda, m, k}, Bv{B, ldb, k, n};
+  if (splittable(m, k, n, s.cutoff)) {
+    plan_node(pp.st, base, Av, Bv, C, ldc, out, s.cutoff);
+    pp.scratch_words = base_scratch_words(s, pp.st.leaves);
+  } else {
+    if (s.splitk > 1 && words(k) > 1) plan_splitk(pp.leaves, Av, Bv, C, ldc, s.splitk);
+    else pp.leaves.push_back(make_desc(Av, Bv, C, ldc, out));
+    pp.scratch_words = base_scratch_words(s, pp.leaves);
+  }
+}
+
 size_t workspace_words(int64_t m, int64_t k, int64_t n, const gf2_schedule& s) {
-  if (!splittable(m, k, n, s.cutoff)) return 0;
-  StrassenPlan pl;
-  plan_node(pl, nullptr, View{nullptr, words(k), m, k}, View{nullptr, words(n), k, n}, nullptr, words(n), OUT_STORE,
-            s.cutoff);
-  return pl.ws_words;
+  ProductPlan pp;
+  plan_product(pp, nullptr, nullptr, words(n), nullptr, words(k), nullptr, words(n), m, k, n, false, s);
+  return pp.total_words();
 }
 
 gf2_status execute(uint64_t* C, int64_t ldc, const uint64_t* A, int64_t lda, const uint64_t* B, int64_t ldb,
                    int64_t m, int64_t k, int64_t n, bool accumulate, const gf2_schedule& s, hipStream_t st) {
-  const int out = accumulate ? OUT_XOR : OUT_STORE;
-  const View Av{A, lda, m, k}, Bv{B, ldb, k, n};
-  if (splittable(m, k, n, s.cutoff)) {
-    const size_t need = workspace_words(m, k, n, s) * 8;
-    WorkspaceLease lease;
-    gf2_status r = lease.acquire(need, st);
-    if (r != GF2_OK) return r;
-    StrassenPlan pl;
-    plan_node(pl, static_cast<uint64_t*>(lease.ptr()), Av, Bv, C, ldc, out, s.cutoff);
-    lease.used();
-    for (const PreOp& p : pl.pre)
+  ProductPlan sizing;
+  plan_product(sizing, nullptr, C, ldc, A, lda, B, ldb, m, k, n, accumulate, s);
+  const size_t need = sizing.total_words() * 8;
+  WorkspaceLease lease;
+  gf2_status r = GF2_OK;
+  if (need > 0 && (r = lease.acquire(need, st)) != GF2_OK) return r;
+  uint64_t* ws = static_cast<uint64_t*>(lease.ptr());
+  ProductPlan pp;
+  plan_product(pp, ws, C, ldc, A, lda, B, ldb, m, k, n, accumulate, s);
+  uint64_t* scratch = ws ? ws + pp.st.ws_words : nullptr;
+  if (need > 0) lease.used();
+  if (!pp.st.leaves.empty()) {
+    for (const PreOp& p : pp.st.pre)
       if ((r = strassen_pre(p.kind, p.in, p.out, p.ldo, p.R, p.Wd, st)) != GF2_OK) return r;
-    if ((r = run_base(s, pl.leaves, st)) != GF2_OK) return r;
-    for (const PostOp& p : pl.post)   // children were pushed before their parent
+    if ((r = run_base(s, pp.st.leaves, scratch, st)) != GF2_OK) return r;
+    for (const PostOp& p : pp.st.post)   // children were pushed before their parent
       if ((r = strassen_post(p.P, p.ldp, p.c, p.mode, st)) != GF2_OK) return r;
     return GF2_OK;
   }
-  std::vector<MulDesc> ds;
-  if (s.splitk > 1 && words(k) > 1) {
-    if (!accumulate) {
-      gf2_status r = fill_zero(OView{C, ldc, m, words(n), tail_of(n)}, st);
-      if (r != GF2_OK) return r;
-    }
-    plan_splitk(ds, Av, Bv, C, ldc, s.splitk);
-  } else {
-    ds.push_back(make_desc(Av, Bv, C, ldc, out));
-  }
-  return run_base(s, ds, st);
+  if (s.splitk > 1 && words(k) > 1 && !accumulate)
+    if ((r = fill_zero(OView{C, ldc, m, words(n), tail_of(n)}, st)) != GF2_OK) return r;
+  return run_base(s, pp.leaves, scratch, st);
 }
 
 gf2_status mul_impl(uint64_t* C, int64_t ldc, const uint64_t* A, int64_t lda, const uint64_t* B, int64_t ldb,
@@ -414,6 +448,8 @@ gf2_status gf2_mul_sched(uint64_t* C, int64_t ldc, const uint64_t* A, int64_t ld
 int32_t gf2_kernel_variants(int32_t kernel) {
   switch (kernel) {
     case GF2_KERNEL_M4RM: return m4rm_num_variants();
+    case GF2_KERNEL_MFMA: return 1;
+    case GF2_KERNEL_CUBIC: return 1;
     default: return 0;
   }
 }

@@ -63,6 +63,14 @@ gf2_status m4rm_launch_group(const MulDesc* descs, int count, int variant, hipSt
 gf2_status m4rm_launch_list(const MulDesc* dev_descs, const int* dev_tile_start, int count, int64_t total_tiles,
                             int variant, hipStream_t s);
 
+// Exact int8 matrix-core base case (mfma.hip).
+int64_t mfma_tiles(const MulDesc& d);
+gf2_status mfma_launch_group(const MulDesc* descs, int count, hipStream_t s);
+
+// Popcount base case with B transposed into scratch (cubic.hip).
+size_t cubic_scratch_words(const MulDesc& d);
+gf2_status cubic_launch(const MulDesc& d, uint64_t* scratch, hipStream_t s);
+
 // Element-wise XOR passes (xorops.hip).
 // A window of a packed matrix with virtual zero padding: rows >= rows and words >= wds
 // read as zero; the word wds-1 is ANDed with ``tail``.

@@ -1,0 +1,60 @@
+"""GPU parity of the other base cases (int8 matrix core, popcount) against the CPU oracle."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from gf2_testutil import run_and_check
+
+
+@pytest.fixture(scope="module")
+def g():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_0811_1714_amd as g
+    g.lib()
+    return g
+
+
+def S(kernel, variant=0, cutoff=0, splitk=1):
+    import paper_0811_1714_amd as g
+    return g.Schedule(kernel, variant, cutoff, splitk)
+
+
+MFMA_SHAPES = [(1, 1, 1), (32, 32, 32), (33, 65, 31), (256, 256, 256), (257, 300, 511), (1024, 1024, 1024),
+               (100, 4096, 70), (700, 129, 1300)]
+
+
+@pytest.mark.parametrize("m,k,n", MFMA_SHAPES)
+def test_mfma_parity_grid(g, m, k, n):
+    print(f"mfma {(m, k, n)}", flush=True)
+    run_and_check(g, m, k, n, schedule=S(g.KERNEL_MFMA), seed=m + 2 * k + 3 * n, lda_pad=1, ldb_pad=2, ldc_pad=1)
+
+
+def test_mfma_addmul_splitk_strassen(g):
+    print("mfma addmul / split-k / strassen", flush=True)
+    run_and_check(g, 300, 700, 500, schedule=S(g.KERNEL_MFMA), accumulate=True, seed=21, ldc_pad=1)
+    run_and_check(g, 200, 5000, 129, schedule=S(g.KERNEL_MFMA, 0, 0, 8), seed=22)
+    base = run_and_check(g, 1500, 1300, 1100, schedule=S(g.KERNEL_M4RM), seed=23)
+    got = run_and_check(g, 1500, 1300, 1100, schedule=S(g.KERNEL_MFMA, 0, 300), seed=23)
+    assert np.array_equal(base, got)
+
+
+CUBIC_SHAPES = [(1, 1, 1), (5, 64, 64), (17, 65, 1), (64, 130, 129), (333, 1000, 200), (1024, 1024, 1024),
+                (4095, 6553, 129), (100, 300, 64)]
+
+
+@pytest.mark.parametrize("m,k,n", CUBIC_SHAPES)
+def test_cubic_popcount_grid(g, m, k, n):
+    print(f"cubic {(m, k, n)}", flush=True)
+    run_and_check(g, m, k, n, schedule=S(g.KERNEL_CUBIC), seed=m + 5 * k + 7 * n, lda_pad=2, ldb_pad=1, ldc_pad=1)
+
+
+def test_cubic_addmul_splitk_strassen(g):
+    print("cubic addmul / split-k / strassen", flush=True)
+    run_and_check(g, 300, 700, 500, schedule=S(g.KERNEL_CUBIC), accumulate=True, seed=31, ldc_pad=1)
+    run_and_check(g, 200, 5000, 129, schedule=S(g.KERNEL_CUBIC, 0, 0, 8), seed=32)
+    base = run_and_check(g, 900, 1300, 700, schedule=S(g.KERNEL_M4RM), seed=33)
+    got = run_and_check(g, 900, 1300, 700, schedule=S(g.KERNEL_CUBIC, 0, 300), seed=33)
+    assert np.array_equal(base, got)
