@@ -90,6 +90,45 @@ gf2_status gf2_mul_sched(uint64_t* C, int64_t ldc, const uint64_t* A, int64_t ld
                          int64_t ldb, int64_t m, int64_t k, int64_t n, int32_t accumulate,
                          const gf2_schedule* sched, void* stream);
 
+/* The fixed list of candidate schedules that the autotuner and the schedule model
+ * choose from (the batched executor's per-product choices).  gf2_candidate copies
+ * entry `index` into *out. */
+int32_t gf2_num_candidates(void);
+gf2_status gf2_candidate(int32_t index, gf2_schedule* out);
+
+/* ---- Batched products ----
+ * Many independent products in one go: the base-case tiles of every product run in
+ * one persistent kernel that pulls tiles (longest first) from an atomic queue;
+ * Strassen-Winograd pre/post passes and split-K zero fills are separate kernels
+ * around it, and products whose schedule is not a persistent-kernel variant run in
+ * grouped launches beside it.  gf2_mul_batched captures this sequence in a HIP
+ * graph on first sight of a batch (keyed by every pointer, shape and schedule) and
+ * replays the graph afterwards. */
+typedef struct gf2_problem {
+  const uint64_t* A;
+  const uint64_t* B;
+  uint64_t* C;
+  int64_t m, k, n;
+  int64_t lda, ldb, ldc;
+  int32_t accumulate; /* 0: C := A*B, 1: C := C + A*B */
+  int32_t schedule;   /* index into the candidate list, or -1: library chooses */
+} gf2_problem;
+
+/* `probs` is a host array of `count` problems (copied).  Every problem is validated
+ * as gf2_mul validates its arguments; in addition no C may overlap another product's
+ * C, A or B (A and B may be shared).  On error nothing is enqueued. */
+gf2_status gf2_mul_batched(const gf2_problem* probs, int64_t count, void* stream);
+
+/* Explicit plans: create (validates, chooses schedules, allocates and uploads the
+ * descriptors and workspace; synchronous), execute (enqueues launches only, no
+ * allocation or host synchronisation, so it may be captured), destroy. */
+typedef struct gf2_batch_plan_s* gf2_batch_plan;
+gf2_status gf2_batch_plan_create(const gf2_problem* probs, int64_t count, gf2_batch_plan* out);
+gf2_status gf2_batch_plan_execute(gf2_batch_plan plan, void* stream);
+gf2_status gf2_batch_plan_destroy(gf2_batch_plan plan);
+/* Schedule index chosen for problem i of the plan (-1 on bad arguments). */
+int32_t gf2_batch_plan_schedule(gf2_batch_plan plan, int64_t i);
+
 /* Number of tile variants of a base kernel (0 for an unknown kernel). */
 int32_t gf2_kernel_variants(int32_t kernel);
 

@@ -68,6 +68,19 @@ def lib():
     L.gf2_trace_read.argtypes = [ctypes.c_void_p, I64, ctypes.POINTER(I64)]
     L.gf2_trace_read.restype = ctypes.c_int
     L.gf2_trace_clear.restype = None
+    L.gf2_num_candidates.restype = I32
+    L.gf2_candidate.argtypes = [I32, ctypes.POINTER(Schedule)]
+    L.gf2_candidate.restype = ctypes.c_int
+    L.gf2_mul_batched.argtypes = [ctypes.c_void_p, I64, P]
+    L.gf2_mul_batched.restype = ctypes.c_int
+    L.gf2_batch_plan_create.argtypes = [ctypes.c_void_p, I64, ctypes.POINTER(ctypes.c_void_p)]
+    L.gf2_batch_plan_create.restype = ctypes.c_int
+    L.gf2_batch_plan_execute.argtypes = [ctypes.c_void_p, P]
+    L.gf2_batch_plan_execute.restype = ctypes.c_int
+    L.gf2_batch_plan_destroy.argtypes = [ctypes.c_void_p]
+    L.gf2_batch_plan_destroy.restype = ctypes.c_int
+    L.gf2_batch_plan_schedule.argtypes = [ctypes.c_void_p, I64]
+    L.gf2_batch_plan_schedule.restype = I32
     _LIB = L
     return L
 
@@ -125,6 +138,72 @@ def mul(C, A, B, m, k, n, *, accumulate=False, schedule=None, stream=None):
     pb, ldb = _mat(B)
     mul_ptr(pc, ldc, pa, lda, pb, ldb, m, k, n, accumulate=accumulate, schedule=schedule, stream=stream)
     return C
+
+
+class Problem(ctypes.Structure):
+    """One product of a batch (mirrors gf2_problem)."""
+    _fields_ = [("A", ctypes.c_void_p), ("B", ctypes.c_void_p), ("C", ctypes.c_void_p),
+                ("m", ctypes.c_int64), ("k", ctypes.c_int64), ("n", ctypes.c_int64),
+                ("lda", ctypes.c_int64), ("ldb", ctypes.c_int64), ("ldc", ctypes.c_int64),
+                ("accumulate", ctypes.c_int32), ("schedule", ctypes.c_int32)]
+
+
+def problem(C, A, B, m, k, n, *, accumulate=False, schedule=-1):
+    """A batch entry over tensors (see ``mul``)."""
+    pc, ldc = _mat(C)
+    pa, lda = _mat(A)
+    pb, ldb = _mat(B)
+    return Problem(pa, pb, pc, m, k, n, lda, ldb, ldc, int(accumulate), int(schedule))
+
+
+def _problem_array(problems):
+    arr = (Problem * len(problems))()
+    for i, p in enumerate(problems):
+        arr[i] = p
+    return arr
+
+
+def mul_batched(problems, stream=None):
+    """Run a list of ``Problem`` through the persistent batched executor (graph cached per batch)."""
+    arr = _problem_array(problems)
+    _check(lib().gf2_mul_batched(arr, len(problems), _stream_handle(stream)))
+
+
+class BatchPlan:
+    """Explicit batch plan: built once (synchronous), executed any number of times."""
+
+    def __init__(self, problems):
+        self._arr = _problem_array(problems)
+        self.handle = ctypes.c_void_p(0)
+        _check(lib().gf2_batch_plan_create(self._arr, len(problems), ctypes.byref(self.handle)))
+        self.count = len(problems)
+
+    def execute(self, stream=None):
+        _check(lib().gf2_batch_plan_execute(self.handle, _stream_handle(stream)))
+
+    def schedule(self, i):
+        return int(lib().gf2_batch_plan_schedule(self.handle, i))
+
+    def destroy(self):
+        if self.handle:
+            _check(lib().gf2_batch_plan_destroy(self.handle))
+            self.handle = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def num_candidates() -> int:
+    return int(lib().gf2_num_candidates())
+
+
+def candidate(i: int) -> Schedule:
+    s = Schedule()
+    _check(lib().gf2_candidate(i, ctypes.byref(s)))
+    return s
 
 
 class TraceRecord(ctypes.Structure):

@@ -5,6 +5,7 @@
 #include <cstdlib>
 #include <algorithm>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <vector>
 
@@ -409,6 +410,9 @@ gf2_status execute(uint64_t* C, int64_t ldc, const uint64_t* A, int64_t lda, con
   return run_base(s, pp.leaves, scratch, st);
 }
 
+int num_candidates_fwd() { return num_candidates(); }
+const gf2_schedule& candidate_fwd(int i) { return candidate(i); }
+
 gf2_status mul_impl(uint64_t* C, int64_t ldc, const uint64_t* A, int64_t lda, const uint64_t* B, int64_t ldb,
                     int64_t m, int64_t k, int64_t n, bool accumulate, const gf2_schedule* sched, void* stream) {
   g_err[0] = 0;
@@ -420,6 +424,238 @@ gf2_status mul_impl(uint64_t* C, int64_t ldc, const uint64_t* A, int64_t lda, co
   if (k == 0) return accumulate ? GF2_OK : fill_zero(OView{C, ldc, m, words(n), tail_of(n)}, st);
   const gf2_schedule s = resolve(sched, m, k, n);
   return execute(C, ldc, A, lda, B, ldb, m, k, n, accumulate, s, st);
+}
+
+
+// ---------------------------------------------------------------- batched products
+
+struct BatchPlanImpl {
+  std::vector<gf2_problem> probs;
+  std::vector<int32_t> sched;
+  int device = 0;
+  uint64_t* ws = nullptr;            // Strassen temporaries of all products, then base scratch
+  MulDesc* d_descs = nullptr;
+  BatchItem* d_items = nullptr;
+  int* d_counter = nullptr;
+  int n_items = 0, grid = 0;
+  uint64_t* scratch = nullptr;
+  double work = 0;
+  std::vector<OView> fills;
+  std::vector<PreOp> pre;
+  std::vector<PostOp> post;
+  struct Side {
+    gf2_schedule s;
+    std::vector<MulDesc> ds;
+  };
+  std::vector<Side> sides;
+  hipGraphExec_t exec = nullptr;
+
+  ~BatchPlanImpl() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (ws) (void)hipFree(ws);
+    if (d_descs) (void)hipFree(d_descs);
+    if (d_items) (void)hipFree(d_items);
+    if (d_counter) (void)hipFree(d_counter);
+  }
+
+  gf2_status enqueue(hipStream_t s) const {
+    gf2_status r;
+    for (const OView& o : fills)
+      if ((r = fill_zero(o, s)) != GF2_OK) return r;
+    for (const PreOp& p : pre)
+      if ((r = strassen_pre(p.kind, p.in, p.out, p.ldo, p.R, p.Wd, s)) != GF2_OK) return r;
+    {
+      TraceScope tr(GF2_TRACE_BATCH, n_items, work, s);
+      if ((r = m4rm_launch_persistent(d_descs, d_items, n_items, d_counter, grid, s)) != GF2_OK) return r;
+    }
+    for (const Side& sd : sides)
+      if ((r = run_base(sd.s, sd.ds, scratch, s)) != GF2_OK) return r;
+    for (const PostOp& p : post)
+      if ((r = strassen_post(p.P, p.ldp, p.c, p.mode, s)) != GF2_OK) return r;
+    return GF2_OK;
+  }
+};
+
+struct Interval {
+  uintptr_t lo, hi;
+};
+
+gf2_status validate_batch(const gf2_problem* probs, int64_t count) {
+  if (count < 0) return set_error(GF2_ERR_INVALID_ARG, "negative batch count");
+  if (count > 0 && !probs) return set_error(GF2_ERR_INVALID_ARG, "problems array is NULL");
+  if (count > (int64_t(1) << 24)) return set_error(GF2_ERR_UNSUPPORTED, "batch larger than 2^24 products");
+  std::vector<Interval> cs, ro;
+  for (int64_t i = 0; i < count; ++i) {
+    const gf2_problem& p = probs[i];
+    gf2_status r = validate(p.C, p.ldc, p.A, p.lda, p.B, p.ldb, p.m, p.k, p.n);
+    if (r != GF2_OK) return set_error(r, "problem %lld: %s", (long long)i, g_err);
+    if (p.schedule < -1 || p.schedule >= num_candidates_fwd())
+      return set_error(GF2_ERR_INVALID_ARG, "problem %lld: schedule %d out of range", (long long)i, p.schedule);
+    if (p.m == 0 || p.n == 0) continue;
+    cs.push_back({(uintptr_t)p.C, (uintptr_t)p.C + (uintptr_t)extent_bytes(p.m, p.ldc, words(p.n))});
+    if (p.k > 0) {
+      ro.push_back({(uintptr_t)p.A, (uintptr_t)p.A + (uintptr_t)extent_bytes(p.m, p.lda, words(p.k))});
+      ro.push_back({(uintptr_t)p.B, (uintptr_t)p.B + (uintptr_t)extent_bytes(p.k, p.ldb, words(p.n))});
+    }
+  }
+  auto by_lo = [](const Interval& x, const Interval& y) { return x.lo < y.lo; };
+  std::sort(cs.begin(), cs.end(), by_lo);
+  for (size_t i = 1; i < cs.size(); ++i)
+    if (cs[i].lo < cs[i - 1].hi) return set_error(GF2_ERR_ALIAS, "two outputs of the batch overlap");
+  // Union of the read-only ranges, then each output against it.
+  std::sort(ro.begin(), ro.end(), by_lo);
+  std::vector<Interval> uni;
+  for (const Interval& x : ro) {
+    if (!uni.empty() && x.lo <= uni.back().hi) uni.back().hi = std::max(uni.back().hi, x.hi);
+    else uni.push_back(x);
+  }
+  for (const Interval& c : cs) {
+    auto it = std::upper_bound(uni.begin(), uni.end(), c, by_lo);   // first range starting after c.lo
+    if (it != uni.end() && it->lo < c.hi) return set_error(GF2_ERR_ALIAS, "an output overlaps an input of the batch");
+    if (it != uni.begin() && std::prev(it)->hi > c.lo)
+      return set_error(GF2_ERR_ALIAS, "an output overlaps an input of the batch");
+  }
+  return GF2_OK;
+}
+
+double tile_cost(const MulDesc& d, int variant, int tm) {
+  const int64_t bm = m4rm_tile_rows(variant);
+  const int64_t rows = std::min<int64_t>(bm, d.m - (int64_t)tm * bm);
+  return (double)((d.k + 15) / 16) * (double)(rows + 256);
+}
+
+gf2_status build_batch_plan(const gf2_problem* probs, int64_t count, BatchPlanImpl& P) {
+  gf2_status r = validate_batch(probs, count);
+  if (r != GF2_OK) return r;
+  if ((r = hip_check(hipGetDevice(&P.device), "hipGetDevice")) != GF2_OK) return r;
+  P.probs.assign(probs, probs + count);
+  P.sched.resize(count);
+  // Pass 1: schedules and workspace sizes.
+  std::vector<size_t> ws_off(count + 1, 0);
+  size_t scratch_words = 0;
+  for (int64_t i = 0; i < count; ++i) {
+    const gf2_problem& p = probs[i];
+    P.sched[i] = p.schedule >= 0 ? p.schedule : choose_candidate(p.m, p.k, p.n);
+    size_t w = 0;
+    if (p.m > 0 && p.n > 0 && p.k > 0) {
+      ProductPlan pp;
+      plan_product(pp, nullptr, p.C, p.ldc, p.A, p.lda, p.B, p.ldb, p.m, p.k, p.n, p.accumulate != 0,
+                   candidate_fwd(P.sched[i]));
+      w = pp.st.ws_words;
+      scratch_words = std::max(scratch_words, pp.scratch_words);
+    }
+    ws_off[i + 1] = ws_off[i] + w;
+  }
+  const size_t total = ws_off[count] + scratch_words;
+  if (total > 0) {
+    if (fault_alloc()) return set_error(GF2_ERR_ALLOC, "injected allocation failure (GF2_FAULT_ALLOC)");
+    if (hipMalloc(&P.ws, total * 8) != hipSuccess) {
+      P.ws = nullptr;
+      return set_error(GF2_ERR_ALLOC, "hipMalloc of %zu bytes of batch workspace failed", total * 8);
+    }
+  }
+  P.scratch = P.ws ? P.ws + ws_off[count] : nullptr;
+  // Pass 2: descriptors, queue items, side launches, fills, Strassen passes.
+  std::vector<MulDesc> descs;
+  std::vector<BatchItem> items;
+  std::vector<double> cost;
+  auto route = [&](const gf2_schedule& s, const std::vector<MulDesc>& leaves) {
+    if (s.kernel == GF2_KERNEL_M4RM && m4rm_batchable(s.variant)) {
+      for (const MulDesc& d : leaves) {
+        const int di = (int)descs.size();
+        descs.push_back(d);
+        const int64_t bm = m4rm_tile_rows(s.variant), tw = m4rm_tile_words(s.variant);
+        const int64_t tms = (d.m + bm - 1) / bm, tns = (words(d.n) + tw - 1) / tw;
+        P.work += (double)d.m * ((d.k + 7) / 8) * (double)words(d.n);
+        for (int64_t tm = 0; tm < tms; ++tm)
+          for (int64_t tn = 0; tn < tns; ++tn) {
+            items.push_back(BatchItem{di, (int32_t)tm, (int32_t)tn, s.variant});
+            cost.push_back(tile_cost(d, s.variant, (int)tm));
+          }
+      }
+      return;
+    }
+    for (auto& sd : P.sides)
+      if (sd.s.kernel == s.kernel && sd.s.variant == s.variant) {
+        sd.ds.insert(sd.ds.end(), leaves.begin(), leaves.end());
+        return;
+      }
+    P.sides.push_back({s, leaves});
+  };
+  for (int64_t i = 0; i < count; ++i) {
+    const gf2_problem& p = probs[i];
+    if (p.m == 0 || p.n == 0) continue;
+    const gf2_schedule& s = candidate_fwd(P.sched[i]);
+    if (p.k == 0) {
+      if (!p.accumulate) P.fills.push_back(OView{p.C, p.ldc, p.m, words(p.n), tail_of(p.n)});
+      continue;
+    }
+    ProductPlan pp;
+    plan_product(pp, P.ws ? P.ws + ws_off[i] : nullptr, p.C, p.ldc, p.A, p.lda, p.B, p.ldb, p.m, p.k, p.n,
+                 p.accumulate != 0, s);
+    if (!pp.st.leaves.empty()) {
+      P.pre.insert(P.pre.end(), pp.st.pre.begin(), pp.st.pre.end());
+      P.post.insert(P.post.end(), pp.st.post.begin(), pp.st.post.end());
+      route(s, pp.st.leaves);
+    } else {
+      if (s.splitk > 1 && words(p.k) > 1 && !p.accumulate)
+        P.fills.push_back(OView{p.C, p.ldc, p.m, words(p.n), tail_of(p.n)});
+      route(s, pp.leaves);
+    }
+  }
+  // Longest tiles first, so the queue ends with short work.
+  std::vector<size_t> order(items.size());
+  for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(), [&](size_t x, size_t y) { return cost[x] > cost[y]; });
+  std::vector<BatchItem> sorted(items.size());
+  for (size_t i = 0; i < order.size(); ++i) sorted[i] = items[order[i]];
+  if (sorted.size() > (size_t)INT32_MAX) return set_error(GF2_ERR_UNSUPPORTED, "too many tiles in one batch");
+  P.n_items = (int)sorted.size();
+  int cus = 0;
+  if ((r = hip_check(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, P.device),
+                     "hipDeviceGetAttribute")) != GF2_OK)
+    return r;
+  P.grid = std::max(1, std::min(cus, P.n_items));
+  auto upload = [&](void** dst, const void* src, size_t bytes) -> gf2_status {
+    if (hipMalloc(dst, bytes ? bytes : 8) != hipSuccess) {
+      *dst = nullptr;
+      return set_error(GF2_ERR_ALLOC, "hipMalloc of %zu bytes for batch descriptors failed", bytes);
+    }
+    return bytes ? hip_check(hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice), "hipMemcpy") : GF2_OK;
+  };
+  if ((r = upload((void**)&P.d_descs, descs.data(), descs.size() * sizeof(MulDesc))) != GF2_OK) return r;
+  if ((r = upload((void**)&P.d_items, sorted.data(), sorted.size() * sizeof(BatchItem))) != GF2_OK) return r;
+  if ((r = upload((void**)&P.d_counter, nullptr, 0)) != GF2_OK) return r;
+  return GF2_OK;
+}
+
+// Graph capture of a plan's launches on a private stream.
+gf2_status capture_plan(BatchPlanImpl& P) {
+  hipStream_t cs = nullptr;
+  gf2_status r = hip_check(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking), "hipStreamCreate");
+  if (r != GF2_OK) return r;
+  hipGraph_t graph = nullptr;
+  trace_suspend(true);
+  r = hip_check(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+  if (r == GF2_OK) {
+    gf2_status er = P.enqueue(cs);
+    gf2_status ec = hip_check(hipStreamEndCapture(cs, &graph), "hipStreamEndCapture");
+    r = er != GF2_OK ? er : ec;
+  }
+  trace_suspend(false);
+  if (r == GF2_OK) r = hip_check(hipGraphInstantiate(&P.exec, graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+  if (graph) (void)hipGraphDestroy(graph);
+  (void)hipStreamDestroy(cs);
+  return r;
+}
+
+std::mutex g_batch_mu;
+std::vector<std::unique_ptr<BatchPlanImpl>> g_batch_cache;
+constexpr size_t kBatchCacheMax = 8;
+
+bool same_batch(const BatchPlanImpl& P, const gf2_problem* probs, int64_t count, int device) {
+  return P.device == device && (int64_t)P.probs.size() == count &&
+         std::memcmp(P.probs.data(), probs, sizeof(gf2_problem) * (size_t)count) == 0;
 }
 
 }  // namespace
@@ -443,6 +679,71 @@ gf2_status gf2_mul_sched(uint64_t* C, int64_t ldc, const uint64_t* A, int64_t ld
                          int64_t m, int64_t k, int64_t n, int32_t accumulate, const gf2_schedule* sched,
                          void* stream) {
   return mul_impl(C, ldc, A, lda, B, ldb, m, k, n, accumulate != 0, sched, stream);
+}
+
+gf2_status gf2_mul_batched(const gf2_problem* probs, int64_t count, void* stream) {
+  g_err[0] = 0;
+  if (count == 0) return GF2_OK;
+  gf2_status r = validate_batch(probs, count);
+  if (r != GF2_OK) return r;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int dev = 0;
+  if ((r = hip_check(hipGetDevice(&dev), "hipGetDevice")) != GF2_OK) return r;
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  BatchPlanImpl* plan = nullptr;
+  if (probs)
+    for (auto& p : g_batch_cache)
+      if (same_batch(*p, probs, count, dev)) { plan = p.get(); break; }
+  if (!plan) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if ((r = hip_check(hipStreamIsCapturing(st, &cs), "hipStreamIsCapturing")) != GF2_OK) return r;
+    if (cs != hipStreamCaptureStatusNone)
+      return set_error(GF2_ERR_CAPTURE, "a new batch cannot be planned under stream capture; use gf2_batch_plan_*");
+    auto P = std::make_unique<BatchPlanImpl>();
+    if ((r = build_batch_plan(probs, count, *P)) != GF2_OK) return r;
+    if ((r = capture_plan(*P)) != GF2_OK) return r;
+    if (g_batch_cache.size() >= kBatchCacheMax) {
+      if ((r = hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize")) != GF2_OK) return r;
+      g_batch_cache.clear();
+    }
+    g_batch_cache.push_back(std::move(P));
+    plan = g_batch_cache.back().get();
+  }
+  TraceScope tr(GF2_TRACE_BATCH, plan->n_items, plan->work, st);
+  return hip_check(hipGraphLaunch(plan->exec, st), "hipGraphLaunch");
+}
+
+struct gf2_batch_plan_s {
+  BatchPlanImpl impl;
+};
+
+gf2_status gf2_batch_plan_create(const gf2_problem* probs, int64_t count, gf2_batch_plan* out) {
+  g_err[0] = 0;
+  if (!out) return set_error(GF2_ERR_INVALID_ARG, "output plan pointer is NULL");
+  *out = nullptr;
+  auto p = std::make_unique<gf2_batch_plan_s>();
+  gf2_status r = build_batch_plan(probs, count, p->impl);
+  if (r != GF2_OK) return r;
+  *out = p.release();
+  return GF2_OK;
+}
+
+gf2_status gf2_batch_plan_execute(gf2_batch_plan plan, void* stream) {
+  g_err[0] = 0;
+  if (!plan) return set_error(GF2_ERR_INVALID_ARG, "plan is NULL");
+  return plan->impl.enqueue(static_cast<hipStream_t>(stream));
+}
+
+gf2_status gf2_batch_plan_destroy(gf2_batch_plan plan) {
+  if (!plan) return GF2_OK;
+  gf2_status r = hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize");
+  delete plan;
+  return r;
+}
+
+int32_t gf2_batch_plan_schedule(gf2_batch_plan plan, int64_t i) {
+  if (!plan || i < 0 || i >= (int64_t)plan->impl.sched.size()) return -1;
+  return plan->impl.sched[i];
 }
 
 int32_t gf2_kernel_variants(int32_t kernel) {
@@ -484,6 +785,11 @@ const char* gf2_status_string(gf2_status s) {
 const char* gf2_last_error(void) { return g_err; }
 
 void gf2_shutdown(void) {
+  {
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    if (!g_batch_cache.empty()) (void)hipDeviceSynchronize();
+    g_batch_cache.clear();
+  }
   for (auto& d : g_dev) {
     std::lock_guard<std::mutex> g(d.mu);
     if (d.base) (void)hipFree(d.base);

@@ -44,6 +44,13 @@ class TraceScope {
   hipEvent_t e0_ = nullptr;
 };
 bool trace_on();
+void trace_suspend(bool on);   // no event records while a graph is being captured
+
+// Candidate schedules (sched.cpp).
+int num_candidates();
+const gf2_schedule& candidate(int i);
+// Candidate index for a product when the caller leaves the choice to the library.
+int choose_candidate(int64_t m, int64_t k, int64_t n);
 
 // ---- kernels (each .hip file owns its launches) ----
 // Products launched together with descriptors passed by value in the kernel arguments.
@@ -62,6 +69,13 @@ int64_t m4rm_tiles(const MulDesc& d, int variant);
 gf2_status m4rm_launch_group(const MulDesc* descs, int count, int variant, hipStream_t s);
 gf2_status m4rm_launch_list(const MulDesc* dev_descs, const int* dev_tile_start, int count, int64_t total_tiles,
                             int variant, hipStream_t s);
+// One queue item of the persistent batch kernel: a C tile of descriptor ``desc``.
+struct BatchItem {
+  int32_t desc, tm, tn, variant;
+};
+bool m4rm_batchable(int variant);   // can run inside the persistent kernel
+gf2_status m4rm_launch_persistent(const MulDesc* dev_descs, const BatchItem* dev_items, int nitems, int* dev_counter,
+                                  int grid, hipStream_t s);
 
 // Exact int8 matrix-core base case (mfma.hip).
 int64_t mfma_tiles(const MulDesc& d);

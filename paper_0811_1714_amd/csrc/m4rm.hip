@@ -422,20 +422,52 @@ struct Variant {
   void (*list)(const MulDesc*, const int*, int);
 };
 
-using V0 = PolicyT2<16, 12, 2>;   // t=2, BM 1536 x 1024 columns, 16 waves
+// Variants 1..4 (the two-table tiles of 1024 down to 128 rows) can run inside the
+// persistent batch kernel; with only these the kernel fits 128 VGPRs without spills.
+using V0 = PolicyT2<16, 12, 2>;   // t=2, BM 1536 x 1024 columns
 using V1 = PolicyT2<16, 8, 4>;    // t=2, BM 1024
 using V2 = PolicyT2<16, 4, 4>;    // t=2, BM 512
-using V3 = PolicyT2<8, 4, 4>;     // t=2, BM 256
-using V4 = PolicyT1<16, 48>;      // t=1, BM 768 x 2048 columns, 16 waves
-using V5 = PolicyT2<8, 24, 4>;    // t=2, BM 1536, 8 waves
-using V6 = PolicyT2<8, 16, 4>;    // t=2, BM 1024, 8 waves
-using V7 = PolicyT2<16, 8, 2>;    // t=2, BM 1024, two lookups in flight
-using V8 = PolicyT2<8, 24, 6>;    // t=2, BM 1536, 8 waves, six in flight
+using V3 = PolicyT2<16, 2, 2>;    // t=2, BM 256
+using V4 = PolicyT2<16, 1, 1>;    // t=2, BM 128
+using V5 = PolicyT1<16, 48>;      // t=1, BM 768 x 2048 columns
+using V6 = PolicyT1<16, 32>;      // t=1, BM 512
+using V7 = PolicyT2<8, 4, 4>;     // t=2, BM 256, 8 waves
+using V8 = PolicyT1<8, 32>;       // t=1, BM 256, 8 waves
+using V9 = PolicyT1<4, 32>;       // t=1, BM 128, 4 waves
 #define GF2_V(P) { P::NT, P::BM, P::TW, m4rm_group<P>, m4rm_list<P> }
 const Variant kVariants[] = {GF2_V(V0), GF2_V(V1), GF2_V(V2), GF2_V(V3), GF2_V(V4),
-                             GF2_V(V5), GF2_V(V6), GF2_V(V7), GF2_V(V8)};
+                             GF2_V(V5), GF2_V(V6), GF2_V(V7), GF2_V(V8), GF2_V(V9)};
 #undef GF2_V
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
+
+// Persistent batch kernel: one workgroup per compute unit pulls tile items from an
+// atomic queue (ordered longest first) until it runs dry; every item names its product
+// and one of the 16-wave variants.  Each tile ends on a barrier, so LDS is free for the
+// next item.
+__global__ __launch_bounds__(1024) void m4rm_persistent(const MulDesc* __restrict__ ds,
+                                                        const BatchItem* __restrict__ items, int nitems,
+                                                        int* __restrict__ counter) {
+  __shared__ uint4 tab[2 * TABLE_BYTES / 16];
+  __shared__ int next;
+  char* t = reinterpret_cast<char*>(tab);
+  for (;;) {
+    if (threadIdx.x == 0) next = atomicAdd(counter, 1);
+    __syncthreads();
+    const int i = next;
+    __syncthreads();
+    if (i >= nitems) break;
+    const BatchItem it = items[i];
+    const MulDesc d = ds[it.desc];
+    switch (it.variant) {
+      case 1: V1::run(d, it.tm, it.tn, t); break;
+      case 2: V2::run(d, it.tm, it.tn, t); break;
+      case 3: V3::run(d, it.tm, it.tn, t); break;
+      default: V4::run(d, it.tm, it.tn, t); break;
+    }
+  }
+}
+
+__global__ void reset_counter(int* c) { *c = 0; }
 
 const Variant& variant_of(int v) { return kVariants[(v < 0 || v >= kNumVariants) ? 0 : v]; }
 
@@ -475,6 +507,17 @@ gf2_status m4rm_launch_group(const MulDesc* descs, int count, int variant, hipSt
     if (st != GF2_OK) return st;
   }
   return GF2_OK;
+}
+
+bool m4rm_batchable(int variant) { return variant >= 1 && variant <= 4; }
+
+gf2_status m4rm_launch_persistent(const MulDesc* dev_descs, const BatchItem* dev_items, int nitems, int* dev_counter,
+                                  int grid, hipStream_t s) {
+  hipLaunchKernelGGL(reset_counter, dim3(1), dim3(1), 0, s, dev_counter);
+  gf2_status st = hip_check(hipGetLastError(), "reset_counter launch");
+  if (st != GF2_OK || nitems == 0) return st;
+  hipLaunchKernelGGL(m4rm_persistent, dim3(grid), dim3(1024), 0, s, dev_descs, dev_items, nitems, dev_counter);
+  return hip_check(hipGetLastError(), "m4rm_persistent launch");
 }
 
 gf2_status m4rm_launch_list(const MulDesc* dev_descs, const int* dev_tile_start, int count, int64_t total_tiles,

@@ -13,11 +13,13 @@ struct Rec {
   hipEvent_t e0, e1;
 };
 std::atomic<bool> g_on{false};
+thread_local bool g_suspended = false;
 std::mutex g_mu;
 std::vector<Rec> g_recs;
 }  // namespace
 
-bool trace_on() { return g_on.load(std::memory_order_relaxed); }
+bool trace_on() { return g_on.load(std::memory_order_relaxed) && !g_suspended; }
+void trace_suspend(bool on) { g_suspended = on; }
 
 TraceScope::TraceScope(int kind, int items, double work, hipStream_t s) : kind_(kind), items_(items), work_(work), s_(s) {
   if (!trace_on()) return;

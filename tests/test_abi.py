@@ -87,3 +87,22 @@ def test_workspace_sizing_matches_plan():
     s = g.Schedule(g.KERNEL_M4RM, 0, 512, 1)
     assert g.workspace_bytes(1024, 1024, 1024, s) == 15 * 512 * 8 * 8
     assert g.workspace_bytes(1024, 1024, 1024, g.Schedule(g.KERNEL_M4RM, 0, 0, 1)) == 0
+
+
+def test_batch_validation_without_device():
+    L = g.lib()
+
+    def prob(C, A, B, m=5, k=5, n=5, ld=1, sched=-1):
+        return g.Problem(A, B, C, m, k, n, ld, ld, ld, 0, sched)
+
+    def run(probs):
+        arr = (g.Problem * len(probs))(*probs)
+        h = ctypes.c_void_p(0)
+        return L.gf2_batch_plan_create(arr, len(probs), ctypes.byref(h))
+
+    assert run([prob(0x10000, 0x20000, 0x30000, m=-1)]) == 1
+    assert run([prob(0x10000, 0x20000, 0x30000, sched=99)]) == 1
+    assert run([prob(0x10000, 0x20000, 0x30000), prob(0x10000 + 16, 0x40000, 0x50000)]) == 2   # C's overlap
+    assert run([prob(0x10000, 0x20000, 0x30000), prob(0x60000, 0x10000, 0x50000)]) == 2        # C is another's A
+    assert L.gf2_mul_batched(None, 3, None) == 1
+    assert L.gf2_num_candidates() >= 8
