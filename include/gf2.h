@@ -129,6 +129,57 @@ gf2_status gf2_batch_plan_destroy(gf2_batch_plan plan);
 /* Schedule index chosen for problem i of the plan (-1 on bad arguments). */
 int32_t gf2_batch_plan_schedule(gf2_batch_plan plan, int64_t i);
 
+/* ---- Schedule policy, autotuner, schedule model ----
+ * How the library chooses a schedule when the caller gives none:
+ *   GF2_POLICY_FIXED    the built-in heuristic (tile height vs table-build cost);
+ *   GF2_POLICY_AUTOTUNE time every candidate once per shape bucket (powers of 2^(1/2)
+ *                       of m, k, n), cache the fastest; falls back to FIXED under capture;
+ *   GF2_POLICY_MODEL    the schedule model set by gf2_set_model (argmin of its predicted
+ *                       log runtimes); falls back to FIXED when no model is set.
+ * Every schedule gives the same bits; the policy only changes the speed. */
+enum { GF2_POLICY_FIXED = 0, GF2_POLICY_AUTOTUNE = 1, GF2_POLICY_MODEL = 2 };
+gf2_status gf2_set_policy(int32_t policy);
+int32_t gf2_get_policy(void);
+
+/* Time every candidate schedule on an m x k by k x n product whose operands the
+ * library fills with Bernoulli(density) bits on the device.  ms[i] (if not NULL,
+ * gf2_num_candidates() entries) receives the median of `reps` timed runs after one
+ * warm-up (a candidate that cannot run gets a negative value); *best the fastest
+ * index.  Synchronises the device.  The result also enters the autotune cache. */
+gf2_status gf2_autotune(int64_t m, int64_t k, int64_t n, double density, int32_t reps, float* ms, int32_t* best);
+/* Autotune cache persistence (text file: one "m_bucket k_bucket n_bucket index" line per entry). */
+gf2_status gf2_autotune_save(const char* path);
+gf2_status gf2_autotune_load(const char* path);
+void gf2_autotune_clear(void);
+
+/* ---- Schedule model kernels ----
+ * A float32 MLP: 4 inputs (log2 m, log2 k, log2 n, density, each standardised) ->
+ * three hidden layers of 64 with ReLU -> gf2_num_candidates() outputs, the predicted
+ * (standardised) log runtimes of the candidate schedules.  Parameters are one flat
+ * float array, layer by layer, W (fan_in x fan_out, row-major) then b.  All pointers
+ * below are device pointers; X is batch x 4, Y and T and M are batch x outputs.
+ * acts: 3 * batch * 64 floats (pre-activations, written by forward, read by
+ * backward); scratch: gf2_mlp_scratch_floats(batch) floats.  The loss is the mean
+ * over observed entries (M = 1) of (Y - T)^2; grads receives its gradient.  Adam
+ * follows Kingma and Ba with bias correction; `step` counts from 1.  Reductions run
+ * in a fixed order, so results are reproducible. */
+int64_t gf2_mlp_param_count(void);
+int64_t gf2_mlp_scratch_floats(int64_t batch);
+gf2_status gf2_mlp_forward(const float* params, const float* X, int64_t batch, float* Y, float* acts, void* stream);
+gf2_status gf2_mlp_backward(const float* params, const float* X, int64_t batch, const float* acts, const float* Y,
+                            const float* T, const float* M, float* grads, float* scratch, float* loss, void* stream);
+gf2_status gf2_mlp_adam(float* params, const float* grads, float* m, float* v, int64_t count, int32_t step, float lr,
+                        float beta1, float beta2, float eps, void* stream);
+/* out[b] = argmin over allowed outputs of Y[b] (allowed: device mask of outputs, or NULL for all). */
+gf2_status gf2_mlp_argmin(const float* Y, int64_t batch, const uint8_t* allowed, int32_t* out, void* stream);
+/* Install the schedule model used by GF2_POLICY_MODEL: host arrays, copied.  norm holds
+ * the mean[4] then std[4] of the raw features (log2 m, log2 k, log2 n, density).
+ * count must equal gf2_mlp_param_count().  NULL params removes the model. */
+gf2_status gf2_set_model(const float* params, int64_t count, const float* norm);
+/* Candidate the current policy picks for a product of this shape (batch != 0: only
+ * schedules the persistent kernel can run). */
+int32_t gf2_choose_schedule(int64_t m, int64_t k, int64_t n, int32_t batch);
+
 /* Number of tile variants of a base kernel (0 for an unknown kernel). */
 int32_t gf2_kernel_variants(int32_t kernel);
 

@@ -81,6 +81,32 @@ def lib():
     L.gf2_batch_plan_destroy.restype = ctypes.c_int
     L.gf2_batch_plan_schedule.argtypes = [ctypes.c_void_p, I64]
     L.gf2_batch_plan_schedule.restype = I32
+    F = ctypes.c_float
+    L.gf2_set_policy.argtypes = [I32]
+    L.gf2_set_policy.restype = ctypes.c_int
+    L.gf2_get_policy.restype = I32
+    L.gf2_choose_schedule.argtypes = [I64, I64, I64, I32]
+    L.gf2_choose_schedule.restype = I32
+    L.gf2_autotune.argtypes = [I64, I64, I64, ctypes.c_double, I32, P, ctypes.POINTER(I32)]
+    L.gf2_autotune.restype = ctypes.c_int
+    L.gf2_autotune_save.argtypes = [ctypes.c_char_p]
+    L.gf2_autotune_save.restype = ctypes.c_int
+    L.gf2_autotune_load.argtypes = [ctypes.c_char_p]
+    L.gf2_autotune_load.restype = ctypes.c_int
+    L.gf2_autotune_clear.restype = None
+    L.gf2_mlp_param_count.restype = I64
+    L.gf2_mlp_scratch_floats.argtypes = [I64]
+    L.gf2_mlp_scratch_floats.restype = I64
+    L.gf2_mlp_forward.argtypes = [P, P, I64, P, P, P]
+    L.gf2_mlp_forward.restype = ctypes.c_int
+    L.gf2_mlp_backward.argtypes = [P, P, I64, P, P, P, P, P, P, P, P]
+    L.gf2_mlp_backward.restype = ctypes.c_int
+    L.gf2_mlp_adam.argtypes = [P, P, P, P, I64, I32, F, F, F, F, P]
+    L.gf2_mlp_adam.restype = ctypes.c_int
+    L.gf2_mlp_argmin.argtypes = [P, I64, P, P, P]
+    L.gf2_mlp_argmin.restype = ctypes.c_int
+    L.gf2_set_model.argtypes = [P, I64, P]
+    L.gf2_set_model.restype = ctypes.c_int
     _LIB = L
     return L
 
@@ -227,6 +253,91 @@ def trace_read(max_records: int = 1 << 16):
 
 def trace_clear():
     lib().gf2_trace_clear()
+
+
+POLICY_FIXED, POLICY_AUTOTUNE, POLICY_MODEL = 0, 1, 2
+
+
+def set_policy(policy: int):
+    _check(lib().gf2_set_policy(policy))
+
+
+def get_policy() -> int:
+    return int(lib().gf2_get_policy())
+
+
+def choose_schedule(m, k, n, batch=False) -> int:
+    return int(lib().gf2_choose_schedule(m, k, n, int(batch)))
+
+
+def autotune(m, k, n, density=0.5, reps=3):
+    """Time every candidate schedule on an m x k x n product; returns (ms array, best index).
+    Negative entries mark candidates that could not run."""
+    import numpy as np
+    ms = np.zeros(num_candidates(), dtype=np.float32)
+    best = ctypes.c_int32(-1)
+    _check(lib().gf2_autotune(m, k, n, float(density), int(reps), ms.ctypes.data_as(ctypes.c_void_p),
+                              ctypes.byref(best)))
+    return ms, best.value
+
+
+def autotune_save(path):
+    _check(lib().gf2_autotune_save(str(path).encode()))
+
+
+def autotune_load(path):
+    _check(lib().gf2_autotune_load(str(path).encode()))
+
+
+def autotune_clear():
+    lib().gf2_autotune_clear()
+
+
+def mlp_param_count() -> int:
+    return int(lib().gf2_mlp_param_count())
+
+
+def mlp_scratch_floats(batch: int) -> int:
+    return int(lib().gf2_mlp_scratch_floats(batch))
+
+
+def _f(t):
+    """Device pointer of a float32 (or uint8 / int32) CUDA tensor, or NULL."""
+    if t is None:
+        return ctypes.c_void_p(0)
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous CUDA tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def mlp_forward(params, X, Y, acts, stream=None):
+    _check(lib().gf2_mlp_forward(_f(params), _f(X), X.shape[0], _f(Y), _f(acts), _stream_handle(stream)))
+
+
+def mlp_backward(params, X, acts, Y, T, M, grads, scratch, loss=None, stream=None):
+    _check(lib().gf2_mlp_backward(_f(params), _f(X), X.shape[0], _f(acts), _f(Y), _f(T), _f(M), _f(grads),
+                                  _f(scratch), _f(loss), _stream_handle(stream)))
+
+
+def mlp_adam(params, grads, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    _check(lib().gf2_mlp_adam(_f(params), _f(grads), _f(m), _f(v), params.numel(), int(step), float(lr),
+                              float(beta1), float(beta2), float(eps), _stream_handle(stream)))
+
+
+def mlp_argmin(Y, out, allowed=None, stream=None):
+    _check(lib().gf2_mlp_argmin(_f(Y), Y.shape[0], _f(allowed), _f(out), _stream_handle(stream)))
+
+
+def set_model(params, norm=None):
+    """Install a schedule model (host float32 arrays) for POLICY_MODEL; ``params=None`` removes it."""
+    import numpy as np
+    if params is None:
+        _check(lib().gf2_set_model(None, 0, None))
+        return
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    nrm = None if norm is None else np.ascontiguousarray(norm, dtype=np.float32)
+    _check(lib().gf2_set_model(p.ctypes.data_as(ctypes.c_void_p), p.size,
+                               nrm.ctypes.data_as(ctypes.c_void_p) if nrm is not None else None))
 
 
 def kernel_variants(kernel: int) -> int:

@@ -4,7 +4,11 @@
 #include <cstdio>
 #include <cstdlib>
 #include <algorithm>
+#include <atomic>
+#include <cmath>
 #include <cstring>
+#include <fstream>
+#include <map>
 #include <memory>
 #include <mutex>
 #include <vector>
@@ -151,11 +155,15 @@ gf2_schedule default_schedule(int64_t m, int64_t k, int64_t n) {
   return s;
 }
 
-gf2_schedule resolve(const gf2_schedule* req, int64_t m, int64_t k, int64_t n) {
+gf2_schedule resolve(const gf2_schedule* req, int64_t m, int64_t k, int64_t n, hipStream_t st) {
   gf2_schedule s = default_schedule(m, k, n);
   {
     std::lock_guard<std::mutex> g(g_sched_mu);
     if (!req && g_has_override) req = &g_override;
+  }
+  if (!req) {
+    const int c = choose_candidate(m, k, n, false, st);
+    if (c >= 0) s = candidate(c);
   }
   if (req) {
     if (req->kernel != GF2_KERNEL_AUTO) s.kernel = req->kernel;
@@ -422,10 +430,129 @@ gf2_status mul_impl(uint64_t* C, int64_t ldc, const uint64_t* A, int64_t lda, co
   if (m == 0 || n == 0) return GF2_OK;
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (k == 0) return accumulate ? GF2_OK : fill_zero(OView{C, ldc, m, words(n), tail_of(n)}, st);
-  const gf2_schedule s = resolve(sched, m, k, n);
+  const gf2_schedule s = resolve(sched, m, k, n, st);
   return execute(C, ldc, A, lda, B, ldb, m, k, n, accumulate, s, st);
 }
 
+
+// ---------------------------------------------------------------- policy and autotuner
+std::atomic<int> g_policy{GF2_POLICY_FIXED};
+
+struct TuneKey {
+  int bm, bk, bn;
+  bool operator<(const TuneKey& o) const { return bm != o.bm ? bm < o.bm : bk != o.bk ? bk < o.bk : bn < o.bn; }
+};
+int tune_bucket(int64_t x) { return (int)std::lround(2.0 * std::log2((double)(x > 0 ? x : 1))); }
+std::mutex g_tune_mu;
+std::map<TuneKey, std::vector<float>> g_tune;
+
+struct TuneScratch {
+  uint64_t* buf = nullptr;
+  size_t words = 0;
+  hipStream_t stream = nullptr;
+  int dev = -1;
+} g_tscr;
+
+gf2_status autotune_shape(int64_t m, int64_t k, int64_t n, double density, int reps, std::vector<float>& ms) {
+  const int S = num_candidates();
+  ms.assign(S, -1.f);
+  if (m <= 0 || k <= 0 || n <= 0 || m > INT32_MAX || k > INT32_MAX || n > INT32_MAX)
+    return set_error(GF2_ERR_INVALID_ARG, "autotune: dimensions must be in [1, 2^31)");
+  if (reps < 1) reps = 1;
+  int dev = 0;
+  gf2_status r = hip_check(hipGetDevice(&dev), "hipGetDevice");
+  if (r != GF2_OK) return r;
+  const int64_t Wk = words(k), Wn = words(n);
+  const size_t need = (size_t)(m * Wk + k * Wn + m * Wn);
+  if (g_tscr.dev != dev) {
+    g_tscr = TuneScratch{};
+    g_tscr.dev = dev;
+  }
+  if (!g_tscr.stream && (r = hip_check(hipStreamCreateWithFlags(&g_tscr.stream, hipStreamNonBlocking),
+                                       "hipStreamCreate")) != GF2_OK)
+    return r;
+  if (need > g_tscr.words) {
+    if ((r = hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize")) != GF2_OK) return r;
+    if (g_tscr.buf) (void)hipFree(g_tscr.buf);
+    g_tscr.buf = nullptr;
+    g_tscr.words = 0;
+    if (hipMalloc(&g_tscr.buf, need * 8) != hipSuccess)
+      return set_error(GF2_ERR_ALLOC, "autotune: hipMalloc of %zu bytes failed", need * 8);
+    g_tscr.words = need;
+  }
+  uint64_t* A = g_tscr.buf;
+  uint64_t* B = A + m * Wk;
+  uint64_t* C = B + k * Wn;
+  hipStream_t st = g_tscr.stream;
+  if ((r = fill_random(A, m * Wk, 0x1234567ull, density, st)) != GF2_OK) return r;
+  if ((r = fill_random(B, k * Wn, 0x7654321ull, density, st)) != GF2_OK) return r;
+  hipEvent_t e0, e1;
+  if ((r = hip_check(hipEventCreate(&e0), "hipEventCreate")) != GF2_OK) return r;
+  if ((r = hip_check(hipEventCreate(&e1), "hipEventCreate")) != GF2_OK) { (void)hipEventDestroy(e0); return r; }
+  std::vector<float> t(reps);
+  for (int c = 0; c < S; ++c) {
+    const gf2_schedule& s = candidate(c);
+    if (execute(C, Wn, A, Wk, B, Wn, m, k, n, false, s, st) != GF2_OK) continue;   // warm-up
+    bool ok = true;
+    for (int i = 0; i < reps && ok; ++i) {
+      ok = hipEventRecord(e0, st) == hipSuccess && execute(C, Wn, A, Wk, B, Wn, m, k, n, false, s, st) == GF2_OK &&
+           hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+           hipEventElapsedTime(&t[i], e0, e1) == hipSuccess;
+    }
+    if (!ok) continue;
+    std::sort(t.begin(), t.end());
+    ms[c] = t[reps / 2];
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  g_err[0] = 0;
+  {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune[TuneKey{tune_bucket(m), tune_bucket(k), tune_bucket(n)}] = ms;
+  }
+  return hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+}
+
+int argmin_allowed(const std::vector<float>& v, bool batch) {
+  int best = -1;
+  for (int c = 0; c < (int)v.size(); ++c) {
+    if (v[c] < 0 || (batch && !batch_allowed(c))) continue;
+    if (best < 0 || v[c] < v[best]) best = c;
+  }
+  return best;
+}
+
+}  // namespace
+
+int choose_candidate(int64_t m, int64_t k, int64_t n, bool batch, hipStream_t s) {
+  const int policy = g_policy.load();
+  if (policy == GF2_POLICY_MODEL) {
+    std::vector<float> y(num_candidates());
+    if (model_predict(m, k, n, 0.5, y.data())) {
+      int best = -1;
+      for (int c = 0; c < (int)y.size(); ++c)
+        if ((!batch || batch_allowed(c)) && (best < 0 || y[c] < y[best])) best = c;
+      if (best >= 0) return best;
+    }
+  } else if (policy == GF2_POLICY_AUTOTUNE && m > 0 && k > 0 && n > 0) {
+    std::vector<float> ms;
+    {
+      std::lock_guard<std::mutex> g(g_tune_mu);
+      auto it = g_tune.find(TuneKey{tune_bucket(m), tune_bucket(k), tune_bucket(n)});
+      if (it != g_tune.end()) ms = it->second;
+    }
+    if (ms.empty()) {
+      hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+      if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone)
+        autotune_shape(m, k, n, 0.5, 3, ms);
+    }
+    const int best = ms.empty() ? -1 : argmin_allowed(ms, batch);
+    if (best >= 0) return best;
+  }
+  return batch ? fixed_candidate(m, k, n) : -1;
+}
+
+namespace {
 
 // ---------------------------------------------------------------- batched products
 
@@ -533,9 +660,24 @@ gf2_status build_batch_plan(const gf2_problem* probs, int64_t count, BatchPlanIm
   // Pass 1: schedules and workspace sizes.
   std::vector<size_t> ws_off(count + 1, 0);
   size_t scratch_words = 0;
+  std::vector<int> model_pick;
+  if (g_policy.load() == GF2_POLICY_MODEL && model_available()) {
+    std::vector<float> feats;
+    for (int64_t i = 0; i < count; ++i)
+      if (probs[i].schedule < 0)
+        feats.insert(feats.end(), {(float)std::log2((double)std::max<int64_t>(probs[i].m, 1)),
+                                   (float)std::log2((double)std::max<int64_t>(probs[i].k, 1)),
+                                   (float)std::log2((double)std::max<int64_t>(probs[i].n, 1)), 0.5f});
+    std::vector<uint8_t> allowed(num_candidates());
+    for (int c = 0; c < num_candidates(); ++c) allowed[c] = batch_allowed(c) ? 1 : 0;
+    if ((r = model_choose_batch(feats, allowed.data(), model_pick)) != GF2_OK) return r;
+  }
+  size_t pick = 0;
   for (int64_t i = 0; i < count; ++i) {
     const gf2_problem& p = probs[i];
-    P.sched[i] = p.schedule >= 0 ? p.schedule : choose_candidate(p.m, p.k, p.n);
+    if (p.schedule >= 0) P.sched[i] = p.schedule;
+    else if (!model_pick.empty() && model_pick[pick] >= 0) P.sched[i] = model_pick[pick++];
+    else P.sched[i] = choose_candidate(p.m, p.k, p.n, true, nullptr);
     size_t w = 0;
     if (p.m > 0 && p.n > 0 && p.k > 0) {
       ProductPlan pp;
@@ -746,6 +888,69 @@ int32_t gf2_batch_plan_schedule(gf2_batch_plan plan, int64_t i) {
   return plan->impl.sched[i];
 }
 
+gf2_status gf2_set_policy(int32_t policy) {
+  if (policy < GF2_POLICY_FIXED || policy > GF2_POLICY_MODEL)
+    return set_error(GF2_ERR_INVALID_ARG, "unknown policy %d", policy);
+  g_policy.store(policy);
+  return GF2_OK;
+}
+
+int32_t gf2_get_policy(void) { return g_policy.load(); }
+
+int32_t gf2_choose_schedule(int64_t m, int64_t k, int64_t n, int32_t batch) {
+  if (m < 0 || k < 0 || n < 0) return -1;
+  const int c = choose_candidate(m, k, n, batch != 0, nullptr);
+  return c >= 0 ? c : fixed_candidate(m, k, n);
+}
+
+gf2_status gf2_autotune(int64_t m, int64_t k, int64_t n, double density, int32_t reps, float* ms, int32_t* best) {
+  g_err[0] = 0;
+  if (density < 0 || density > 1) return set_error(GF2_ERR_INVALID_ARG, "density must be in [0, 1]");
+  std::vector<float> v;
+  gf2_status r = autotune_shape(m, k, n, density, reps, v);
+  if (r != GF2_OK) return r;
+  if (ms) std::copy(v.begin(), v.end(), ms);
+  if (best) *best = argmin_allowed(v, false);
+  return GF2_OK;
+}
+
+gf2_status gf2_autotune_save(const char* path) {
+  if (!path) return set_error(GF2_ERR_INVALID_ARG, "path is NULL");
+  std::ofstream f(path);
+  if (!f) return set_error(GF2_ERR_INVALID_ARG, "cannot write %s", path);
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  for (const auto& kv : g_tune) {
+    f << kv.first.bm << ' ' << kv.first.bk << ' ' << kv.first.bn;
+    for (float x : kv.second) f << ' ' << x;
+    f << '\n';
+  }
+  return f ? GF2_OK : set_error(GF2_ERR_INVALID_ARG, "write to %s failed", path);
+}
+
+gf2_status gf2_autotune_load(const char* path) {
+  if (!path) return set_error(GF2_ERR_INVALID_ARG, "path is NULL");
+  std::ifstream f(path);
+  if (!f) return set_error(GF2_ERR_INVALID_ARG, "cannot read %s", path);
+  std::map<TuneKey, std::vector<float>> loaded;
+  TuneKey key;
+  const int S = num_candidates();
+  while (f >> key.bm >> key.bk >> key.bn) {
+    std::vector<float> v(S);
+    for (int c = 0; c < S; ++c)
+      if (!(f >> v[c])) return set_error(GF2_ERR_INVALID_ARG, "%s: truncated entry (cache left unchanged)", path);
+    loaded[key] = v;
+  }
+  if (!f.eof()) return set_error(GF2_ERR_INVALID_ARG, "%s: malformed (cache left unchanged)", path);
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  for (auto& kv : loaded) g_tune[kv.first] = kv.second;
+  return GF2_OK;
+}
+
+void gf2_autotune_clear(void) {
+  std::lock_guard<std::mutex> g(g_tune_mu);
+  g_tune.clear();
+}
+
 int32_t gf2_kernel_variants(int32_t kernel) {
   switch (kernel) {
     case GF2_KERNEL_M4RM: return m4rm_num_variants();
@@ -757,7 +962,7 @@ int32_t gf2_kernel_variants(int32_t kernel) {
 
 size_t gf2_workspace_bytes(int64_t m, int64_t k, int64_t n, const gf2_schedule* sched) {
   if (m <= 0 || k <= 0 || n <= 0) return 0;
-  const gf2_schedule s = resolve(sched, m, k, n);
+  const gf2_schedule s = resolve(sched, m, k, n, nullptr);
   return workspace_words(m, k, n, s) * 8;
 }
 
@@ -785,6 +990,10 @@ const char* gf2_status_string(gf2_status s) {
 const char* gf2_last_error(void) { return g_err; }
 
 void gf2_shutdown(void) {
+  gf2_set_model(nullptr, 0, nullptr);
+  if (g_tscr.buf) (void)hipFree(g_tscr.buf);
+  if (g_tscr.stream) (void)hipStreamDestroy(g_tscr.stream);
+  g_tscr = TuneScratch{};
   {
     std::lock_guard<std::mutex> lk(g_batch_mu);
     if (!g_batch_cache.empty()) (void)hipDeviceSynchronize();

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 #include <cstddef>
+#include <vector>
 #include "gf2.h"
 
 namespace gf2 {
@@ -49,8 +50,16 @@ void trace_suspend(bool on);   // no event records while a graph is being captur
 // Candidate schedules (sched.cpp).
 int num_candidates();
 const gf2_schedule& candidate(int i);
-// Candidate index for a product when the caller leaves the choice to the library.
-int choose_candidate(int64_t m, int64_t k, int64_t n);
+// Candidate index for a product when the caller leaves the choice to the library,
+// under the current policy (fixed heuristic, autotune cache, or schedule model).
+// ``batch`` restricts the choice to schedules the persistent kernel can run.
+int choose_candidate(int64_t m, int64_t k, int64_t n, bool batch, hipStream_t s);
+int fixed_candidate(int64_t m, int64_t k, int64_t n);
+// Schedule model inference on the host copy of the weights: predicted log runtimes.
+bool model_predict(int64_t m, int64_t k, int64_t n, double density, float* out);
+bool model_available();
+gf2_status model_choose_batch(const std::vector<float>& feats_raw, const uint8_t* allowed_host, std::vector<int>& out);
+bool batch_allowed(int candidate);
 
 // ---- kernels (each .hip file owns its launches) ----
 // Products launched together with descriptors passed by value in the kernel arguments.
@@ -85,6 +94,19 @@ gf2_status mfma_launch_group(const MulDesc* descs, int count, hipStream_t s);
 size_t cubic_scratch_words(const MulDesc& d);
 gf2_status cubic_launch(const MulDesc& d, uint64_t* scratch, hipStream_t s);
 
+// Schedule model kernels (mlp.hip).
+int64_t mlp_param_count(int nout);
+int64_t mlp_scratch_floats(int64_t batch, int nout);
+gf2_status mlp_forward(const float* params, const float* X, int64_t batch, int nout, float* Y, float* acts,
+                       hipStream_t s);
+gf2_status mlp_backward(const float* params, const float* X, int64_t batch, int nout, const float* acts,
+                        const float* Y, const float* T, const float* M, float* grads, float* scratch, float* loss,
+                        hipStream_t s);
+gf2_status mlp_adam(float* p, const float* g, float* m, float* v, int64_t n, int32_t step, float lr, float b1,
+                    float b2, float eps, hipStream_t s);
+gf2_status mlp_argmin(const float* Y, int64_t batch, int nout, const uint8_t* allowed, int32_t* out, hipStream_t s);
+void mlp_forward_host(const float* params, const float* x, int nout, float* y);
+
 // Element-wise XOR passes (xorops.hip).
 // A window of a packed matrix with virtual zero padding: rows >= rows and words >= wds
 // read as zero; the word wds-1 is ANDed with ``tail``.
@@ -101,6 +123,7 @@ struct OView {
   uint64_t tail;       // mask for word wds-1 (padding bits written 0 or left unchanged)
 };
 gf2_status fill_zero(const OView& o, hipStream_t s);
+gf2_status fill_random(uint64_t* p, int64_t nwords, uint64_t seed, double density, hipStream_t s);
 // Strassen-Winograd pre-additions (Algorithm 4): from the four quadrants NW, NE, SW, SE
 // of A (kind 0) produce S0..S3, of B (kind 1) produce T0..T3, over R x Wd words.
 gf2_status strassen_pre(int kind, const QView in[4], uint64_t* const out[4], int64_t ldo, int64_t R, int64_t Wd,

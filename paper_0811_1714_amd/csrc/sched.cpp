@@ -1,4 +1,8 @@
 // Candidate schedules and the schedule policy used by single and batched products.
+#include <cmath>
+#include <mutex>
+#include <vector>
+
 #include "gf2_internal.h"
 
 namespace gf2 {
@@ -30,7 +34,7 @@ const gf2_schedule& candidate(int i) { return kCandidates[i]; }
 // that minimises (tiles) x (16-row phases) x (rows per tile + the table build, counted
 // as 256 row lookups per phase) -- the paper's trade-off between block size and the
 // cost of regenerating the tables (Section 3.2), with LDS in place of cache.
-int choose_candidate(int64_t m, int64_t k, int64_t n) {
+int fixed_candidate(int64_t m, int64_t k, int64_t n) {
   int best = 0;
   double best_cost = 0;
   for (int c = 0; c <= 3; ++c) {
@@ -43,6 +47,90 @@ int choose_candidate(int64_t m, int64_t k, int64_t n) {
   return best;
 }
 
+// ---- schedule model: host copy for single products, device copy for batches ----
+namespace {
+std::mutex g_model_mu;
+std::vector<float> g_model;
+float g_norm[8] = {0, 0, 0, 0, 1, 1, 1, 1};
+float* g_model_dev = nullptr;
+int g_model_dev_id = -1;
+}  // namespace
+
+bool model_available() {
+  std::lock_guard<std::mutex> g(g_model_mu);
+  return !g_model.empty();
+}
+
+void model_features(int64_t m, int64_t k, int64_t n, double density, float* x) {
+  const double raw[4] = {std::log2((double)(m > 0 ? m : 1)), std::log2((double)(k > 0 ? k : 1)),
+                         std::log2((double)(n > 0 ? n : 1)), density};
+  for (int i = 0; i < 4; ++i) x[i] = (float)((raw[i] - g_norm[i]) / (g_norm[4 + i] != 0 ? g_norm[4 + i] : 1.0f));
+}
+
+bool model_predict(int64_t m, int64_t k, int64_t n, double density, float* out) {
+  std::lock_guard<std::mutex> g(g_model_mu);
+  if (g_model.empty()) return false;
+  float x[4];
+  model_features(m, k, n, density, x);
+  mlp_forward_host(g_model.data(), x, kNumCandidates, out);
+  return true;
+}
+
+// Device inference for many products: returns the argmin candidates (allowed mask on host).
+gf2_status model_choose_batch(const std::vector<float>& feats_raw, const uint8_t* allowed_host, std::vector<int>& out) {
+  const int64_t nb = (int64_t)feats_raw.size() / 4;
+  out.assign(nb, -1);
+  std::lock_guard<std::mutex> g(g_model_mu);
+  if (g_model.empty() || nb == 0) return GF2_OK;
+  int dev = 0;
+  gf2_status r = hip_check(hipGetDevice(&dev), "hipGetDevice");
+  if (r != GF2_OK) return r;
+  if (g_model_dev && g_model_dev_id != dev) {
+    (void)hipFree(g_model_dev);
+    g_model_dev = nullptr;
+  }
+  if (!g_model_dev) {
+    if (hipMalloc(&g_model_dev, g_model.size() * sizeof(float)) != hipSuccess) {
+      g_model_dev = nullptr;
+      return set_error(GF2_ERR_ALLOC, "hipMalloc for the schedule model failed");
+    }
+    if ((r = hip_check(hipMemcpy(g_model_dev, g_model.data(), g_model.size() * sizeof(float),
+                                 hipMemcpyHostToDevice), "hipMemcpy")) != GF2_OK)
+      return r;
+    g_model_dev_id = dev;
+  }
+  std::vector<float> x(nb * 4);
+  for (int64_t b = 0; b < nb; ++b) {
+    const double raw[4] = {feats_raw[4 * b], feats_raw[4 * b + 1], feats_raw[4 * b + 2], feats_raw[4 * b + 3]};
+    for (int i = 0; i < 4; ++i)
+      x[4 * b + i] = (float)((raw[i] - g_norm[i]) / (g_norm[4 + i] != 0 ? g_norm[4 + i] : 1.0f));
+  }
+  // One allocation: X, Y, acts, allowed, out.
+  const size_t fX = nb * 4, fY = nb * kNumCandidates, fA = 3 * nb * 64;
+  const size_t bytes = (fX + fY + fA) * sizeof(float) + 64 + nb * sizeof(int32_t);
+  char* buf = nullptr;
+  if (hipMalloc(&buf, bytes) != hipSuccess) return set_error(GF2_ERR_ALLOC, "hipMalloc for model inference failed");
+  float* dX = reinterpret_cast<float*>(buf);
+  float* dY = dX + fX;
+  float* dA = dY + fY;
+  uint8_t* dAllowed = reinterpret_cast<uint8_t*>(dA + fA);
+  int32_t* dOut = reinterpret_cast<int32_t*>(dAllowed + 64);
+  std::vector<int32_t> host_out(nb);
+  r = hip_check(hipMemcpy(dX, x.data(), fX * sizeof(float), hipMemcpyHostToDevice), "hipMemcpy");
+  if (r == GF2_OK) r = hip_check(hipMemcpy(dAllowed, allowed_host, kNumCandidates, hipMemcpyHostToDevice), "hipMemcpy");
+  if (r == GF2_OK) r = mlp_forward(g_model_dev, dX, nb, kNumCandidates, dY, dA, nullptr);
+  if (r == GF2_OK) r = mlp_argmin(dY, nb, kNumCandidates, dAllowed, dOut, nullptr);
+  if (r == GF2_OK) r = hip_check(hipMemcpy(host_out.data(), dOut, nb * sizeof(int32_t), hipMemcpyDeviceToHost), "hipMemcpy");
+  (void)hipFree(buf);
+  for (int64_t b = 0; b < nb; ++b) out[b] = host_out[b];
+  return r;
+}
+
+bool batch_allowed(int c) {
+  const gf2_schedule& s = kCandidates[c];
+  return s.kernel == GF2_KERNEL_M4RM && m4rm_batchable(s.variant);
+}
+
 }  // namespace gf2
 
 using namespace gf2;
@@ -50,6 +138,54 @@ using namespace gf2;
 extern "C" {
 
 int32_t gf2_num_candidates(void) { return kNumCandidates; }
+
+int64_t gf2_mlp_param_count(void) { return mlp_param_count(kNumCandidates); }
+int64_t gf2_mlp_scratch_floats(int64_t batch) { return batch < 0 ? 0 : mlp_scratch_floats(batch, kNumCandidates); }
+
+gf2_status gf2_mlp_forward(const float* params, const float* X, int64_t batch, float* Y, float* acts, void* stream) {
+  if (batch < 0 || (batch > 0 && (!params || !X || !Y || !acts)))
+    return set_error(GF2_ERR_INVALID_ARG, "gf2_mlp_forward: bad arguments");
+  return mlp_forward(params, X, batch, kNumCandidates, Y, acts, static_cast<hipStream_t>(stream));
+}
+
+gf2_status gf2_mlp_backward(const float* params, const float* X, int64_t batch, const float* acts, const float* Y,
+                            const float* T, const float* M, float* grads, float* scratch, float* loss, void* stream) {
+  if (batch < 0 || !params || !grads || !scratch || (batch > 0 && (!X || !acts || !Y || !T || !M)))
+    return set_error(GF2_ERR_INVALID_ARG, "gf2_mlp_backward: bad arguments");
+  return mlp_backward(params, X, batch, kNumCandidates, acts, Y, T, M, grads, scratch, loss,
+                      static_cast<hipStream_t>(stream));
+}
+
+gf2_status gf2_mlp_adam(float* params, const float* grads, float* m, float* v, int64_t count, int32_t step, float lr,
+                        float beta1, float beta2, float eps, void* stream) {
+  if (count < 0 || step < 1 || (count > 0 && (!params || !grads || !m || !v)))
+    return set_error(GF2_ERR_INVALID_ARG, "gf2_mlp_adam: bad arguments");
+  return mlp_adam(params, grads, m, v, count, step, lr, beta1, beta2, eps, static_cast<hipStream_t>(stream));
+}
+
+gf2_status gf2_mlp_argmin(const float* Y, int64_t batch, const uint8_t* allowed, int32_t* out, void* stream) {
+  if (batch < 0 || (batch > 0 && (!Y || !out))) return set_error(GF2_ERR_INVALID_ARG, "gf2_mlp_argmin: bad arguments");
+  return mlp_argmin(Y, batch, kNumCandidates, allowed, out, static_cast<hipStream_t>(stream));
+}
+
+gf2_status gf2_set_model(const float* params, int64_t count, const float* norm) {
+  std::lock_guard<std::mutex> g(g_model_mu);
+  if (g_model_dev) {
+    (void)hipFree(g_model_dev);
+    g_model_dev = nullptr;
+    g_model_dev_id = -1;
+  }
+  if (!params) {
+    g_model.clear();
+    return GF2_OK;
+  }
+  if (count != mlp_param_count(kNumCandidates))
+    return set_error(GF2_ERR_INVALID_ARG, "model has %lld parameters, expected %lld", (long long)count,
+                     (long long)mlp_param_count(kNumCandidates));
+  g_model.assign(params, params + count);
+  for (int i = 0; i < 8; ++i) g_norm[i] = norm ? norm[i] : (i < 4 ? 0.f : 1.f);
+  return GF2_OK;
+}
 
 gf2_status gf2_candidate(int32_t index, gf2_schedule* out) {
   if (!out || index < 0 || index >= kNumCandidates)

@@ -140,3 +140,41 @@ gf2_status strassen_post(const uint64_t* const P[7], int64_t ldp, const OView c[
 }
 
 }  // namespace gf2
+
+namespace gf2 {
+namespace {
+// Timing operands: bit j of word w of the buffer is set with probability ``density``,
+// from a hash of (seed, position); padding and stride gaps are ordinary bits here.
+__device__ __forceinline__ uint64_t mix64(uint64_t z) {
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+__global__ void fill_random_kernel(uint64_t* p, int64_t nwords, uint64_t seed, uint32_t thr, int dense) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nwords; i += (int64_t)gridDim.x * blockDim.x) {
+    const uint64_t base = seed + (uint64_t)i * 0x9E3779B97F4A7C15ull;
+    if (dense) {
+      p[i] = mix64(base);
+      continue;
+    }
+    uint64_t w = 0;
+    for (int b = 0; b < 64; b += 2) {
+      const uint64_t r = mix64(base + (uint64_t)b);
+      w |= (uint64_t)((uint32_t)r < thr) << b;
+      w |= (uint64_t)((uint32_t)(r >> 32) < thr) << (b + 1);
+    }
+    p[i] = w;
+  }
+}
+}  // namespace
+
+gf2_status fill_random(uint64_t* p, int64_t nwords, uint64_t seed, double density, hipStream_t s) {
+  if (nwords <= 0) return GF2_OK;
+  const int dense = density >= 0.5 - 1e-12 && density <= 0.5 + 1e-12;
+  const double t = density <= 0 ? 0.0 : (density >= 1 ? 4294967295.0 : density * 4294967296.0);
+  hipLaunchKernelGGL(fill_random_kernel, dim3(grid_for(nwords)), dim3(kThreads), 0, s, p, nwords, seed,
+                     (uint32_t)t, dense);
+  return hip_check(hipGetLastError(), "fill_random launch");
+}
+
+}  // namespace gf2

@@ -1,0 +1,98 @@
+"""GPU checks of the schedule model kernels (against the float64 reference in oracle.mlp),
+the autotuner and the schedule policies (which must never change the bits)."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from oracle import mlp as ref
+from gf2_testutil import run_and_check
+
+
+@pytest.fixture(scope="module")
+def g():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_0811_1714_amd as g
+    g.lib()
+    return g
+
+
+def split_params(flat, S):
+    sizes = [4, 64, 64, 64, S]
+    out, off = [], 0
+    for fi, fo in zip(sizes[:-1], sizes[1:]):
+        out.append(flat[off: off + fi * fo].reshape(fi, fo)); off += fi * fo
+        out.append(flat[off: off + fo]); off += fo
+    assert off == flat.size
+    return out
+
+
+def test_mlp_forward_backward_adam_match_float64_reference(g):
+    import torch
+    S = g.num_candidates()
+    P = g.mlp_param_count()
+    assert P == 4 * 64 + 64 + 2 * (64 * 64 + 64) + 64 * S + S
+    rng = np.random.default_rng(0)
+    batch = 37
+    flat = rng.standard_normal(P).astype(np.float32) * 0.3
+    X = rng.standard_normal((batch, 4)).astype(np.float32)
+    T = rng.standard_normal((batch, S)).astype(np.float32)
+    M = (rng.random((batch, S)) < 0.85).astype(np.float32)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    dp, dX, dT, dM = dev(flat), dev(X), dev(T), dev(M)
+    dY = torch.empty((batch, S), dtype=torch.float32, device="cuda")
+    acts = torch.empty(3 * batch * 64, dtype=torch.float32, device="cuda")
+    grads = torch.empty(P, dtype=torch.float32, device="cuda")
+    scratch = torch.empty(g.mlp_scratch_floats(batch), dtype=torch.float32, device="cuda")
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    print("mlp forward/backward", flush=True)
+    g.mlp_forward(dp, dX, dY, acts)
+    g.mlp_backward(dp, dX, acts, dY, dT, dM, grads, scratch, loss)
+    torch.cuda.synchronize()
+    params = [p.astype(np.float64) for p in split_params(flat.astype(np.float64), S)]
+    Yr, cache = ref.forward(params, X.astype(np.float64))
+    gr = ref.backward(params, cache, Yr, T.astype(np.float64), M.astype(np.float64))
+    np.testing.assert_allclose(dY.cpu().numpy(), Yr, rtol=1e-4, atol=1e-4)
+    assert abs(loss.item() - ref.loss(Yr, T, M)) <= 1e-4 * max(1.0, ref.loss(Yr, T, M))
+    gflat = np.concatenate([x.reshape(-1) for x in gr])
+    got = grads.cpu().numpy().astype(np.float64)
+    err = np.abs(got - gflat) / (np.abs(gflat) + 1e-3 * np.abs(gflat).max())
+    assert err.max() < 1e-3, err.max()
+    # One Adam step against the reference.
+    m0 = torch.zeros(P, dtype=torch.float32, device="cuda")
+    v0 = torch.zeros(P, dtype=torch.float32, device="cuda")
+    g.mlp_adam(dp, grads, m0, v0, step=1, lr=1e-2)
+    torch.cuda.synchronize()
+    newp, _, _ = ref.adam_step([flat.astype(np.float64)], [got], [np.zeros(P)], [np.zeros(P)], 1, lr=1e-2)
+    np.testing.assert_allclose(dp.cpu().numpy(), newp[0], rtol=1e-5, atol=1e-6)
+    # argmin with a mask
+    allowed = torch.zeros(S, dtype=torch.uint8, device="cuda")
+    allowed[[1, 3, 5]] = 1
+    out = torch.empty(batch, dtype=torch.int32, device="cuda")
+    g.mlp_argmin(dY, out, allowed)
+    y = dY.cpu().numpy()
+    sub = np.array([1, 3, 5])
+    assert np.array_equal(out.cpu().numpy(), sub[np.argmin(y[:, sub], axis=1)])
+
+
+def test_autotune_and_policies_keep_bits(g):
+    print("autotune", flush=True)
+    ms, best = g.autotune(700, 900, 1100, density=0.3, reps=2)
+    assert ms.shape == (g.num_candidates(),) and 0 <= best < ms.size and ms[best] > 0
+    assert ms[best] == ms[ms > 0].min()
+    try:
+        base = run_and_check(g, 700, 900, 1100, seed=41)
+        g.set_policy(g.POLICY_AUTOTUNE)
+        assert np.array_equal(run_and_check(g, 700, 900, 1100, seed=41), base)
+        rng = np.random.default_rng(1)
+        g.set_model(rng.standard_normal(g.mlp_param_count()).astype(np.float32),
+                    np.array([9, 9, 9, .25, 2, 2, 2, .2], dtype=np.float32))
+        g.set_policy(g.POLICY_MODEL)
+        assert np.array_equal(run_and_check(g, 700, 900, 1100, seed=41), base)
+        c = g.choose_schedule(700, 900, 1100, batch=True)
+        assert 0 <= c < g.num_candidates()
+    finally:
+        g.set_policy(g.POLICY_FIXED)
+        g.set_model(None)
