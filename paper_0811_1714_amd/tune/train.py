@@ -1,0 +1,154 @@
+"""Train the schedule model on the GPU with the library's own kernels (gf2_mlp_forward,
+gf2_mlp_backward, gf2_mlp_adam), from a timing dataset written by ``tune.timings``.
+
+Inputs: (log2 m, log2 k, log2 n, density), standardised.  Targets: log of each
+candidate's median runtime (ms), standardised over all observed entries; candidates that
+could not run are masked out of the loss.  Evaluation: schedule regret on the held-out
+shapes, t(chosen) / t(fastest) - 1, for the model and for the fixed heuristic.
+
+    python -m paper_0811_1714_amd.tune.train --data timings.npz --out model.npz
+"""
+import argparse
+import json
+import os
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+DEFAULT_MODEL = os.path.join(os.path.dirname(os.path.abspath(__file__)), "schedule_model.npz")
+
+
+def features(dims, dens):
+    return np.column_stack([np.log2(dims.astype(np.float64)), dens.astype(np.float64)])
+
+
+def init_params(S, seed):
+    rng = np.random.default_rng(seed)
+    sizes = [4, 64, 64, 64, S]
+    parts = []
+    for fi, fo in zip(sizes[:-1], sizes[1:]):
+        parts.append((rng.standard_normal((fi, fo)) * np.sqrt(2.0 / fi)).reshape(-1))
+        parts.append(np.zeros(fo))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def regret(ms, choice):
+    """t(choice)/t(best) - 1 per row (rows whose chosen candidate did not run count as inf)."""
+    valid = np.where(ms > 0, ms, np.inf)
+    best = valid.min(axis=1)
+    got = valid[np.arange(len(ms)), choice]
+    return got / best - 1.0
+
+
+def summarize(r):
+    return {"mean": float(np.mean(r)), "median": float(np.median(r)), "p90": float(np.percentile(r, 90)),
+            "within_10pct": float(np.mean(r <= 0.10))}
+
+
+class Trainer:
+    def __init__(self, g, S, batch):
+        import torch
+        self.g, self.S, self.batch = g, S, batch
+        self.P = g.mlp_param_count()
+        f = lambda *shape: torch.zeros(*shape, dtype=torch.float32, device="cuda")
+        self.params = f(self.P)
+        self.grads, self.m, self.v = f(self.P), f(self.P), f(self.P)
+        self.X, self.T, self.M = f(batch, 4), f(batch, S), f(batch, S)
+        self.Y, self.acts = f(batch, S), f(3 * batch * 64)
+        self.scratch = f(g.mlp_scratch_floats(batch))
+        self.loss = f(1)
+        self.step_count = 0
+
+    def step(self, X, T, M, lr):
+        import torch
+        n = X.shape[0]
+        self.X[:n].copy_(torch.from_numpy(X)); self.T[:n].copy_(torch.from_numpy(T))
+        self.M[:n].copy_(torch.from_numpy(M))
+        X_, T_, M_, Y_ = self.X[:n], self.T[:n], self.M[:n], self.Y[:n]
+        self.g.mlp_forward(self.params, X_, Y_, self.acts[:3 * n * 64])
+        self.g.mlp_backward(self.params, X_, self.acts[:3 * n * 64], Y_, T_, M_, self.grads, self.scratch, self.loss)
+        self.step_count += 1
+        self.g.mlp_adam(self.params, self.grads, self.m, self.v, self.step_count, lr=lr)
+
+    def predict(self, X):
+        import torch
+        out = []
+        for s in range(0, len(X), self.batch):
+            xb = X[s: s + self.batch]
+            n = len(xb)
+            self.X[:n].copy_(torch.from_numpy(xb))
+            self.g.mlp_forward(self.params, self.X[:n], self.Y[:n], self.acts[:3 * n * 64])
+            out.append(self.Y[:n].cpu().numpy().copy())
+        return np.concatenate(out) if out else np.zeros((0, self.S), np.float32)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--data", required=True)
+    ap.add_argument("--out", default=DEFAULT_MODEL)
+    ap.add_argument("--epochs", type=int, default=400)
+    ap.add_argument("--batch", type=int, default=512)
+    ap.add_argument("--lr", type=float, default=2e-3)
+    ap.add_argument("--seed", type=int, default=0)
+    args = ap.parse_args()
+    import torch
+    import paper_0811_1714_amd as g
+    g.lib()
+    S = g.num_candidates()
+    d = np.load(args.data)
+    Xtr_raw, Xho_raw = features(d["train_dims"], d["train_density"]), features(d["heldout_dims"], d["heldout_density"])
+    ms_tr, ms_ho = d["train_ms"].astype(np.float64), d["heldout_ms"].astype(np.float64)
+    mean, std = Xtr_raw.mean(axis=0), Xtr_raw.std(axis=0) + 1e-9
+    Mtr = (ms_tr > 0).astype(np.float32)
+    logt = np.where(ms_tr > 0, np.log(np.maximum(ms_tr, 1e-9)), 0.0)
+    tmean = float(logt[Mtr > 0].mean()); tstd = float(logt[Mtr > 0].std() + 1e-9)
+    Ttr = ((logt - tmean) / tstd * Mtr).astype(np.float32)
+    Xtr = ((Xtr_raw - mean) / std).astype(np.float32)
+    Xho = ((Xho_raw - mean) / std).astype(np.float32)
+
+    tr = Trainer(g, S, args.batch)
+    tr.params.copy_(torch.from_numpy(init_params(S, args.seed)))
+    rng = np.random.default_rng(args.seed)
+    n = len(Xtr)
+    history = []
+    for ep in range(args.epochs):
+        lr = args.lr * (0.5 * (1 + np.cos(np.pi * ep / args.epochs)))
+        perm = rng.permutation(n)
+        for s in range(0, n, args.batch):
+            idx = perm[s: s + args.batch]
+            tr.step(Xtr[idx], Ttr[idx], Mtr[idx], lr)
+        if ep % 50 == 0 or ep == args.epochs - 1:
+            torch.cuda.synchronize()
+            pred = tr.predict(Xtr)
+            l = float((((pred - Ttr) * Mtr) ** 2).sum() / Mtr.sum())
+            history.append((ep, l))
+            print(f"epoch {ep}: train mse {l:.4f}", flush=True)
+
+    params = tr.params.cpu().numpy()
+    norm = np.concatenate([mean, std]).astype(np.float32)
+    pred_ho = tr.predict(Xho)
+    allowed = np.array([g.candidate(i).kernel == g.KERNEL_M4RM and 1 <= g.candidate(i).variant <= 4
+                        for i in range(S)])
+    choice_all = np.argmin(pred_ho, axis=1)
+    choice_batch = np.where(allowed, pred_ho, np.inf).argmin(axis=1)
+    g.set_policy(g.POLICY_FIXED)
+    heur = np.array([g.choose_schedule(int(m), int(k), int(nn), batch=True) for m, k, nn in d["heldout_dims"]])
+    ms_ho_batch = np.where(allowed[None, :], ms_ho, -1.0)
+    report = {
+        "train_shapes": int(n), "heldout_shapes": int(len(Xho)), "epochs": args.epochs,
+        "final_train_mse": history[-1][1],
+        "regret_model_all_candidates": summarize(regret(ms_ho, choice_all)),
+        "regret_model_batch_candidates": summarize(regret(ms_ho_batch, choice_batch)),
+        "regret_fixed_heuristic_batch_candidates": summarize(regret(ms_ho_batch, heur)),
+    }
+    np.savez(args.out, params=params, norm=norm, target_mean=tmean, target_std=tstd,
+             history=np.array(history), report=json.dumps(report))
+    print(json.dumps(report), flush=True)
+
+
+if __name__ == "__main__":
+    main()
