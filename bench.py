@@ -43,6 +43,7 @@ def parse():
     ap.add_argument("--sweep-variants", type=int, nargs="*", default=None)
     ap.add_argument("--check-rows", type=int, default=16, help="rows compared with the oracle after timing")
     ap.add_argument("--copy-calibration", action="store_true", help="run a plain 1 GiB device copy (counter scale)")
+    ap.add_argument("--batch", type=int, default=0, help="also time a batch of this many log-uniform products")
     return ap.parse_args()
 
 
@@ -128,6 +129,65 @@ def sweep(g):
                                   "eff_bitops": 2 * n ** 3 / (min(per) * 1e-3)}), flush=True)
         del dA, dB, dC
         torch.cuda.empty_cache()
+
+
+def batch_bench(g, count, steps, warmup, seed=3, lo=64, hi=4096):
+    """Config 4: ``count`` independent products, m, k, n log-uniform in [lo, hi) (Bernoulli(1/2)
+    bits generated on the device).  Times the persistent graph-captured batch against the plain
+    form (one gf2_mul per product, fixed default schedule)."""
+    import torch
+    import synth
+    dims = synth.log_uniform_dims(seed, 4, count, lo, hi)
+    W = lambda c: (int(c) + 63) // 64
+    sizes = [int(m) * W(k) + int(k) * W(n) + int(m) * W(n) for m, k, n in dims]
+    offs = np.concatenate([[0], np.cumsum([(s + 31) // 32 * 32 for s in sizes])])
+    gen = torch.Generator(device="cuda").manual_seed(seed)
+    pool = torch.randint(-(1 << 62), 1 << 62, (int(offs[-1]),), dtype=torch.int64, device="cuda", generator=gen)
+    probs = []
+    for i, (m, k, n) in enumerate(dims):
+        m, k, n = int(m), int(k), int(n)
+        base = int(offs[i])
+        A = pool[base: base + m * W(k)].view(m, W(k))
+        B = pool[base + m * W(k): base + m * W(k) + k * W(n)].view(k, W(n))
+        C = pool[base + m * W(k) + k * W(n): base + sizes[i]].view(m, W(n))
+        probs.append((C, A, B, m, k, n))
+    plist = [g.problem(C, A, B, m, k, n) for (C, A, B, m, k, n) in probs]
+    total_ops = float(sum(2.0 * m * k * n for (_, _, _, m, k, n) in probs))
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, reps):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    out = {"count": count, "total_bitops": total_ops, "pool_bytes": int(offs[-1]) * 8}
+    g.set_policy(g.POLICY_FIXED)
+    out["ms_plain"] = timed(lambda: [g.mul(C, A, B, m, k, n) for (C, A, B, m, k, n) in probs], max(1, steps // 2))
+    out["ms_batched_fixed"] = timed(lambda: g.mul_batched(plist), steps)
+    if os.path.exists(g.DEFAULT_MODEL):
+        g.load_model()
+        g.set_policy(g.POLICY_MODEL)
+        out["ms_batched_model"] = timed(lambda: g.mul_batched(plist), steps)
+        plan = g.BatchPlan(plist)
+        out["model_schedule_histogram"] = np.bincount([plan.schedule(i) for i in range(count)],
+                                                      minlength=g.num_candidates()).tolist()
+        plan.destroy()
+        g.set_policy(g.POLICY_FIXED)
+        g.set_model(None)
+    best = min(v for kk, v in out.items() if kk.startswith("ms_batched"))
+    out["bitops_batched_best"] = total_ops / (best * 1e-3)
+    out["bitops_plain"] = total_ops / (out["ms_plain"] * 1e-3)
+    out["speedup_vs_plain"] = out["ms_plain"] / best
+    if "ms_batched_model" in out:
+        out["model_gain_vs_fixed"] = out["ms_batched_fixed"] / out["ms_batched_model"]
+    return out
 
 
 def cpu_baseline(A, B, n, seconds):
@@ -226,6 +286,10 @@ def main():
                      "word_xors_per_launch": work,
                      "valu_roof_frac": (work / VALU_WORD_XOR_PEAK) / (kms * 1e-3)},
     }
+    if args.batch:
+        del dA, dB, dC
+        torch.cuda.empty_cache()
+        out["batch"] = batch_bench(g, args.batch, max(3, args.steps), 1)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(A, B, n, args.cpu_seconds)
     print(json.dumps(out), flush=True)

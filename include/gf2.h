@@ -147,6 +147,13 @@ int32_t gf2_get_policy(void);
  * warm-up (a candidate that cannot run gets a negative value); *best the fastest
  * index.  Synchronises the device.  The result also enters the autotune cache. */
 gf2_status gf2_autotune(int64_t m, int64_t k, int64_t n, double density, int32_t reps, float* ms, int32_t* best);
+/* Throughput timing: the per-product time of each candidate when R copies of the product
+ * (shared A and B, separate C; R chosen so one batch holds enough work to fill the GPU,
+ * returned in *copies) run as one batch plan.  This is the cost that matters inside
+ * gf2_mul_batched.  ms as in gf2_autotune; candidates are timed in batch form even when
+ * they are not persistent-kernel schedules (they then run as grouped launches). */
+gf2_status gf2_autotune_batch(int64_t m, int64_t k, int64_t n, double density, int32_t reps, float* ms,
+                              int32_t* best, int32_t* copies);
 /* Autotune cache persistence (text file: one "m_bucket k_bucket n_bucket index" line per entry). */
 gf2_status gf2_autotune_save(const char* path);
 gf2_status gf2_autotune_load(const char* path);
@@ -154,8 +161,10 @@ void gf2_autotune_clear(void);
 
 /* ---- Schedule model kernels ----
  * A float32 MLP: 4 inputs (log2 m, log2 k, log2 n, density, each standardised) ->
- * three hidden layers of 64 with ReLU -> gf2_num_candidates() outputs, the predicted
- * (standardised) log runtimes of the candidate schedules.  Parameters are one flat
+ * three hidden layers of 64 with ReLU -> 2 * gf2_num_candidates() outputs: the predicted
+ * (standardised) log runtimes of the candidate schedules for a product on its own
+ * (outputs 0 .. S-1, used by gf2_mul) and per product inside a batch (outputs S .. 2S-1,
+ * used by batch plans; see gf2_autotune_batch).  Parameters are one flat
  * float array, layer by layer, W (fan_in x fan_out, row-major) then b.  All pointers
  * below are device pointers; X is batch x 4, Y and T and M are batch x outputs.
  * acts: 3 * batch * 64 floats (pre-activations, written by forward, read by
@@ -170,7 +179,7 @@ gf2_status gf2_mlp_backward(const float* params, const float* X, int64_t batch, 
                             const float* T, const float* M, float* grads, float* scratch, float* loss, void* stream);
 gf2_status gf2_mlp_adam(float* params, const float* grads, float* m, float* v, int64_t count, int32_t step, float lr,
                         float beta1, float beta2, float eps, void* stream);
-/* out[b] = argmin over allowed outputs of Y[b] (allowed: device mask of outputs, or NULL for all). */
+/* out[b] = argmin over allowed outputs of Y[b] (allowed: device mask of the 2S outputs, or NULL for all). */
 gf2_status gf2_mlp_argmin(const float* Y, int64_t batch, const uint8_t* allowed, int32_t* out, void* stream);
 /* Install the schedule model used by GF2_POLICY_MODEL: host arrays, copied.  norm holds
  * the mean[4] then std[4] of the raw features (log2 m, log2 k, log2 n, density).

@@ -89,6 +89,8 @@ def lib():
     L.gf2_choose_schedule.restype = I32
     L.gf2_autotune.argtypes = [I64, I64, I64, ctypes.c_double, I32, P, ctypes.POINTER(I32)]
     L.gf2_autotune.restype = ctypes.c_int
+    L.gf2_autotune_batch.argtypes = [I64, I64, I64, ctypes.c_double, I32, P, ctypes.POINTER(I32), ctypes.POINTER(I32)]
+    L.gf2_autotune_batch.restype = ctypes.c_int
     L.gf2_autotune_save.argtypes = [ctypes.c_char_p]
     L.gf2_autotune_save.restype = ctypes.c_int
     L.gf2_autotune_load.argtypes = [ctypes.c_char_p]
@@ -281,6 +283,16 @@ def autotune(m, k, n, density=0.5, reps=3):
     return ms, best.value
 
 
+def autotune_batch(m, k, n, density=0.5, reps=3):
+    """Per-product time of every candidate inside a batch of copies; returns (ms, best, copies)."""
+    import numpy as np
+    ms = np.zeros(num_candidates(), dtype=np.float32)
+    best, copies = ctypes.c_int32(-1), ctypes.c_int32(0)
+    _check(lib().gf2_autotune_batch(m, k, n, float(density), int(reps), ms.ctypes.data_as(ctypes.c_void_p),
+                                    ctypes.byref(best), ctypes.byref(copies)))
+    return ms, best.value, copies.value
+
+
 def autotune_save(path):
     _check(lib().gf2_autotune_save(str(path).encode()))
 
@@ -338,6 +350,17 @@ def set_model(params, norm=None):
     nrm = None if norm is None else np.ascontiguousarray(norm, dtype=np.float32)
     _check(lib().gf2_set_model(p.ctypes.data_as(ctypes.c_void_p), p.size,
                                nrm.ctypes.data_as(ctypes.c_void_p) if nrm is not None else None))
+
+
+DEFAULT_MODEL = os.path.join(_HERE, "tune", "schedule_model.npz")
+
+
+def load_model(path=DEFAULT_MODEL):
+    """Install the trained schedule model stored by ``tune.train`` (params + feature norm)."""
+    import numpy as np
+    d = np.load(path)
+    set_model(d["params"], d["norm"])
+    return d
 
 
 def kernel_variants(kernel: int) -> int:

@@ -264,8 +264,6 @@ gf2_status run_base(const gf2_schedule& s, const std::vector<MulDesc>& ds, uint6
   }
 }
 
-struct PreOp { int kind; QView in[4]; uint64_t* out[4]; int64_t ldo, R, Wd; };
-struct PostOp { const uint64_t* P[7]; int64_t ldp; OView c[4]; int mode; };
 
 struct StrassenPlan {
   std::vector<PreOp> pre;
@@ -286,7 +284,7 @@ bool splittable(int64_t m, int64_t k, int64_t n, int64_t cutoff) {
 // post-ops children first; the leaves run all at once in between.  ``base`` == nullptr
 // only sizes the workspace.
 void plan_node(StrassenPlan& pl, uint64_t* base, const View& A, const View& B, uint64_t* C, int64_t ldc,
-               int out_mode, int64_t cutoff) {
+               int out_mode, int64_t cutoff, int depth = 0) {
   const int64_t m = A.rows, k = A.cols, n = B.cols;
   if (!splittable(m, k, n, cutoff)) {
     pl.leaves.push_back(make_desc(A, B, C, ldc, out_mode));
@@ -309,6 +307,7 @@ void plan_node(StrassenPlan& pl, uint64_t* base, const View& A, const View& B, u
 
   PreOp ps;
   ps.kind = 0;
+  ps.depth = depth;
   ps.in[0] = QView{A.p, A.ld, m0, k0w, ~0ull};
   ps.in[1] = QView{A.p + k0w, A.ld, m0, words(k1), tail_of(k1)};
   ps.in[2] = QView{A.p + m0 * A.ld, A.ld, m1, k0w, ~0ull};
@@ -318,6 +317,7 @@ void plan_node(StrassenPlan& pl, uint64_t* base, const View& A, const View& B, u
   pl.pre.push_back(ps);
   PreOp pt;
   pt.kind = 1;
+  pt.depth = depth;
   pt.in[0] = QView{B.p, B.ld, k0, n0w, ~0ull};
   pt.in[1] = QView{B.p + n0w, B.ld, k0, words(n1), tail_of(n1)};
   pt.in[2] = QView{B.p + k0 * B.ld, B.ld, k1, n0w, ~0ull};
@@ -330,13 +330,13 @@ void plan_node(StrassenPlan& pl, uint64_t* base, const View& A, const View& B, u
   const View B_NW{B.p, B.ld, k0, n0}, B_SW{B.p + k0 * B.ld, B.ld, k1, n0}, B_SE{B.p + k0 * B.ld + n0w, B.ld, k1, n1};
   const View S0{S[0], k0w, m0, k0}, S1{S[1], k0w, m0, k0}, S2{S[2], k0w, m0, k0}, S3{S[3], k0w, m0, k1};
   const View T0{T[0], n0w, k0, n0}, T1{T[1], n0w, k0, n0}, T2{T[2], n0w, k0, n0}, T3{T[3], n0w, k1, n0};
-  plan_node(pl, base, A_NW, B_NW, P[0], n0w, OUT_STORE, cutoff);   // P0 = A_NW B_NW
-  plan_node(pl, base, A_NE, B_SW, P[1], n0w, OUT_STORE, cutoff);   // P1 = A_NE B_SW
-  plan_node(pl, base, S3, B_SE, P[2], n0w, OUT_STORE, cutoff);     // P2 = S3 B_SE
-  plan_node(pl, base, A_SE, T3, P[3], n0w, OUT_STORE, cutoff);     // P3 = A_SE T3
-  plan_node(pl, base, S0, T0, P[4], n0w, OUT_STORE, cutoff);       // P4 = S0 T0
-  plan_node(pl, base, S1, T1, P[5], n0w, OUT_STORE, cutoff);       // P5 = S1 T1
-  plan_node(pl, base, S2, T2, P[6], n0w, OUT_STORE, cutoff);       // P6 = S2 T2
+  plan_node(pl, base, A_NW, B_NW, P[0], n0w, OUT_STORE, cutoff, depth + 1);   // P0 = A_NW B_NW
+  plan_node(pl, base, A_NE, B_SW, P[1], n0w, OUT_STORE, cutoff, depth + 1);   // P1 = A_NE B_SW
+  plan_node(pl, base, S3, B_SE, P[2], n0w, OUT_STORE, cutoff, depth + 1);     // P2 = S3 B_SE
+  plan_node(pl, base, A_SE, T3, P[3], n0w, OUT_STORE, cutoff, depth + 1);     // P3 = A_SE T3
+  plan_node(pl, base, S0, T0, P[4], n0w, OUT_STORE, cutoff, depth + 1);       // P4 = S0 T0
+  plan_node(pl, base, S1, T1, P[5], n0w, OUT_STORE, cutoff, depth + 1);       // P5 = S1 T1
+  plan_node(pl, base, S2, T2, P[6], n0w, OUT_STORE, cutoff, depth + 1);       // P6 = S2 T2
 
   PostOp po;
   for (int i = 0; i < 7; ++i) po.P[i] = P[i];
@@ -346,6 +346,7 @@ void plan_node(StrassenPlan& pl, uint64_t* base, const View& A, const View& B, u
   po.c[2] = OView{C + m0 * ldc, ldc, m1, n0w, ~0ull};
   po.c[3] = OView{C + m0 * ldc + n0w, ldc, m1, words(n1), tail_of(n1)};
   po.mode = out_mode;
+  po.depth = depth;
   pl.post.push_back(po);
 }
 
@@ -407,10 +408,10 @@ gf2_status execute(uint64_t* C, int64_t ldc, const uint64_t* A, int64_t lda, con
   if (need > 0) lease.used();
   if (!pp.st.leaves.empty()) {
     for (const PreOp& p : pp.st.pre)
-      if ((r = strassen_pre(p.kind, p.in, p.out, p.ldo, p.R, p.Wd, st)) != GF2_OK) return r;
+      if ((r = strassen_pre(p, st)) != GF2_OK) return r;
     if ((r = run_base(s, pp.st.leaves, scratch, st)) != GF2_OK) return r;
     for (const PostOp& p : pp.st.post)   // children were pushed before their parent
-      if ((r = strassen_post(p.P, p.ldp, p.c, p.mode, st)) != GF2_OK) return r;
+      if ((r = strassen_post(p, st)) != GF2_OK) return r;
     return GF2_OK;
   }
   if (s.splitk > 1 && words(k) > 1 && !accumulate)
@@ -437,6 +438,7 @@ gf2_status mul_impl(uint64_t* C, int64_t ldc, const uint64_t* A, int64_t lda, co
 
 // ---------------------------------------------------------------- policy and autotuner
 std::atomic<int> g_policy{GF2_POLICY_FIXED};
+std::atomic<uint64_t> g_policy_epoch{0};   // bumped whenever a policy, model or tune cache changes
 
 struct TuneKey {
   int bm, bk, bn;
@@ -510,8 +512,14 @@ gf2_status autotune_shape(int64_t m, int64_t k, int64_t n, double density, int r
     std::lock_guard<std::mutex> g(g_tune_mu);
     g_tune[TuneKey{tune_bucket(m), tune_bucket(k), tune_bucket(n)}] = ms;
   }
+  ++g_policy_epoch;
   return hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
 }
+
+struct BatchPlanImpl;
+gf2_status build_batch_plan(const gf2_problem* probs, int64_t count, BatchPlanImpl& P);
+gf2_status autotune_batch_shape(int64_t m, int64_t k, int64_t n, double density, int reps, std::vector<float>& ms,
+                                int& copies);
 
 int argmin_allowed(const std::vector<float>& v, bool batch) {
   int best = -1;
@@ -524,14 +532,18 @@ int argmin_allowed(const std::vector<float>& v, bool batch) {
 
 }  // namespace
 
+void bump_policy_epoch() { ++g_policy_epoch; }
+
 int choose_candidate(int64_t m, int64_t k, int64_t n, bool batch, hipStream_t s) {
   const int policy = g_policy.load();
   if (policy == GF2_POLICY_MODEL) {
-    std::vector<float> y(num_candidates());
+    const int S = num_candidates();
+    std::vector<float> y(2 * S);
     if (model_predict(m, k, n, 0.5, y.data())) {
+      const float* yy = y.data() + (batch ? S : 0);   // latency head or batch-throughput head
       int best = -1;
-      for (int c = 0; c < (int)y.size(); ++c)
-        if ((!batch || batch_allowed(c)) && (best < 0 || y[c] < y[best])) best = c;
+      for (int c = 0; c < S; ++c)
+        if ((!batch || batch_allowed(c)) && (best < 0 || yy[c] < yy[best])) best = c;
       if (best >= 0) return best;
     }
   } else if (policy == GF2_POLICY_AUTOTUNE && m > 0 && k > 0 && n > 0) {
@@ -557,6 +569,7 @@ namespace {
 // ---------------------------------------------------------------- batched products
 
 struct BatchPlanImpl {
+  uint64_t epoch = 0;                // policy epoch the schedules were chosen under
   std::vector<gf2_problem> probs;
   std::vector<int32_t> sched;
   int device = 0;
@@ -570,6 +583,17 @@ struct BatchPlanImpl {
   std::vector<OView> fills;
   std::vector<PreOp> pre;
   std::vector<PostOp> post;
+  // Device copies, pre ops sorted by depth (parents first), post ops deepest first;
+  // each group is one multi-op launch.
+  OView* d_fills = nullptr;
+  PreOp* d_pre = nullptr;
+  PostOp* d_post = nullptr;
+  struct Group {
+    int begin, count;
+    int64_t max_elems;
+  };
+  std::vector<Group> pre_groups, post_groups;
+  int64_t fill_max = 0;
   struct Side {
     gf2_schedule s;
     std::vector<MulDesc> ds;
@@ -583,22 +607,26 @@ struct BatchPlanImpl {
     if (d_descs) (void)hipFree(d_descs);
     if (d_items) (void)hipFree(d_items);
     if (d_counter) (void)hipFree(d_counter);
+    if (d_fills) (void)hipFree(d_fills);
+    if (d_pre) (void)hipFree(d_pre);
+    if (d_post) (void)hipFree(d_post);
   }
 
   gf2_status enqueue(hipStream_t s) const {
     gf2_status r;
-    for (const OView& o : fills)
-      if ((r = fill_zero(o, s)) != GF2_OK) return r;
-    for (const PreOp& p : pre)
-      if ((r = strassen_pre(p.kind, p.in, p.out, p.ldo, p.R, p.Wd, s)) != GF2_OK) return r;
+    for (size_t i = 0; i < fills.size(); i += 65535)   // grid y limit
+      if ((r = fill_zero_multi(d_fills + i, (int)std::min<size_t>(65535, fills.size() - i), fill_max, s)) != GF2_OK)
+        return r;
+    for (const Group& gr : pre_groups)
+      if ((r = strassen_pre_multi(d_pre + gr.begin, gr.count, gr.max_elems, s)) != GF2_OK) return r;
     {
       TraceScope tr(GF2_TRACE_BATCH, n_items, work, s);
       if ((r = m4rm_launch_persistent(d_descs, d_items, n_items, d_counter, grid, s)) != GF2_OK) return r;
     }
     for (const Side& sd : sides)
       if ((r = run_base(sd.s, sd.ds, scratch, s)) != GF2_OK) return r;
-    for (const PostOp& p : post)
-      if ((r = strassen_post(p.P, p.ldp, p.c, p.mode, s)) != GF2_OK) return r;
+    for (const Group& gr : post_groups)
+      if ((r = strassen_post_multi(d_post + gr.begin, gr.count, gr.max_elems, s)) != GF2_OK) return r;
     return GF2_OK;
   }
 };
@@ -655,6 +683,7 @@ gf2_status build_batch_plan(const gf2_problem* probs, int64_t count, BatchPlanIm
   gf2_status r = validate_batch(probs, count);
   if (r != GF2_OK) return r;
   if ((r = hip_check(hipGetDevice(&P.device), "hipGetDevice")) != GF2_OK) return r;
+  P.epoch = g_policy_epoch.load();
   P.probs.assign(probs, probs + count);
   P.sched.resize(count);
   // Pass 1: schedules and workspace sizes.
@@ -768,6 +797,24 @@ gf2_status build_batch_plan(const gf2_problem* probs, int64_t count, BatchPlanIm
   if ((r = upload((void**)&P.d_descs, descs.data(), descs.size() * sizeof(MulDesc))) != GF2_OK) return r;
   if ((r = upload((void**)&P.d_items, sorted.data(), sorted.size() * sizeof(BatchItem))) != GF2_OK) return r;
   if ((r = upload((void**)&P.d_counter, nullptr, 0)) != GF2_OK) return r;
+  // Auxiliary passes: fills in one launch, Strassen passes in one launch per depth.
+  for (const OView& o : P.fills) P.fill_max = std::max(P.fill_max, o.rows * o.wds);
+  std::stable_sort(P.pre.begin(), P.pre.end(), [](const PreOp& x, const PreOp& y) { return x.depth < y.depth; });
+  std::stable_sort(P.post.begin(), P.post.end(), [](const PostOp& x, const PostOp& y) { return x.depth > y.depth; });
+  auto groups = [](const auto& ops, std::vector<BatchPlanImpl::Group>& out, auto elems) {
+    for (int i = 0; i < (int)ops.size();) {
+      int j = i;
+      int64_t mx = 0;
+      while (j < (int)ops.size() && ops[j].depth == ops[i].depth && j - i < 65535) mx = std::max(mx, elems(ops[j++]));
+      out.push_back({i, j - i, mx});
+      i = j;
+    }
+  };
+  groups(P.pre, P.pre_groups, [](const PreOp& o) { return o.R * o.Wd; });
+  groups(P.post, P.post_groups, [](const PostOp& o) { return o.c[0].rows * o.c[0].wds; });
+  if ((r = upload((void**)&P.d_fills, P.fills.data(), P.fills.size() * sizeof(OView))) != GF2_OK) return r;
+  if ((r = upload((void**)&P.d_pre, P.pre.data(), P.pre.size() * sizeof(PreOp))) != GF2_OK) return r;
+  if ((r = upload((void**)&P.d_post, P.post.data(), P.post.size() * sizeof(PostOp))) != GF2_OK) return r;
   return GF2_OK;
 }
 
@@ -795,8 +842,77 @@ std::mutex g_batch_mu;
 std::vector<std::unique_ptr<BatchPlanImpl>> g_batch_cache;
 constexpr size_t kBatchCacheMax = 8;
 
+
+// Per-product time of every candidate inside a batch of R copies of the product.
+gf2_status autotune_batch_shape(int64_t m, int64_t k, int64_t n, double density, int reps, std::vector<float>& ms,
+                                int& copies) {
+  const int S = num_candidates();
+  ms.assign(S, -1.f);
+  if (m <= 0 || k <= 0 || n <= 0 || m > INT32_MAX || k > INT32_MAX || n > INT32_MAX)
+    return set_error(GF2_ERR_INVALID_ARG, "autotune: dimensions must be in [1, 2^31)");
+  if (reps < 1) reps = 1;
+  // Enough copies that even the tallest persistent tile (1024 rows x 16 words) gives ~2048
+  // tiles, i.e. the batch fills every compute unit several times over, as in a real batch.
+  const int64_t Wk = words(k), Wn = words(n);
+  const double vol = (double)m * (double)k * (double)n;
+  const int64_t tiles1024 = ((m + 1023) / 1024) * ((Wn + 15) / 16);
+  int64_t R = std::max<int64_t>((2048 + tiles1024 - 1) / tiles1024, (int64_t)std::llround(8e8 / vol));
+  R = std::max<int64_t>(2, std::min<int64_t>(R, 512));
+  R = std::max<int64_t>(1, std::min<int64_t>(R, (int64_t)((512ll << 20) / (8 * m * Wn))));
+  copies = (int)R;
+  int dev = 0;
+  gf2_status r = hip_check(hipGetDevice(&dev), "hipGetDevice");
+  if (r != GF2_OK) return r;
+  const size_t need = (size_t)(m * Wk + k * Wn + R * m * Wn);
+  if (g_tscr.dev != dev) {
+    g_tscr = TuneScratch{};
+    g_tscr.dev = dev;
+  }
+  if (!g_tscr.stream && (r = hip_check(hipStreamCreateWithFlags(&g_tscr.stream, hipStreamNonBlocking),
+                                       "hipStreamCreate")) != GF2_OK)
+    return r;
+  if (need > g_tscr.words) {
+    if ((r = hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize")) != GF2_OK) return r;
+    if (g_tscr.buf) (void)hipFree(g_tscr.buf);
+    g_tscr.buf = nullptr;
+    g_tscr.words = 0;
+    if (hipMalloc(&g_tscr.buf, need * 8) != hipSuccess)
+      return set_error(GF2_ERR_ALLOC, "autotune: hipMalloc of %zu bytes failed", need * 8);
+    g_tscr.words = need;
+  }
+  uint64_t* A = g_tscr.buf;
+  uint64_t* B = A + m * Wk;
+  uint64_t* C = B + k * Wn;
+  hipStream_t st = g_tscr.stream;
+  if ((r = fill_random(A, m * Wk, 0x1234567ull, density, st)) != GF2_OK) return r;
+  if ((r = fill_random(B, k * Wn, 0x7654321ull, density, st)) != GF2_OK) return r;
+  std::vector<gf2_problem> probs(R);
+  hipEvent_t e0, e1;
+  if ((r = hip_check(hipEventCreate(&e0), "hipEventCreate")) != GF2_OK) return r;
+  if ((r = hip_check(hipEventCreate(&e1), "hipEventCreate")) != GF2_OK) { (void)hipEventDestroy(e0); return r; }
+  std::vector<float> t(reps);
+  for (int c = 0; c < S; ++c) {
+    for (int64_t i = 0; i < R; ++i) probs[i] = gf2_problem{A, B, C + i * m * Wn, m, k, n, Wk, Wn, Wn, 0, c};
+    BatchPlanImpl P;
+    if (build_batch_plan(probs.data(), R, P) != GF2_OK || P.enqueue(st) != GF2_OK) continue;
+    bool ok = true;
+    for (int i = 0; i < reps && ok; ++i) {
+      ok = hipEventRecord(e0, st) == hipSuccess && P.enqueue(st) == GF2_OK && hipEventRecord(e1, st) == hipSuccess &&
+           hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&t[i], e0, e1) == hipSuccess;
+    }
+    if (hipStreamSynchronize(st) != hipSuccess) ok = false;
+    if (!ok) continue;
+    std::sort(t.begin(), t.end());
+    ms[c] = t[reps / 2] / (float)R;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  g_err[0] = 0;
+  return hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
+}
+
 bool same_batch(const BatchPlanImpl& P, const gf2_problem* probs, int64_t count, int device) {
-  return P.device == device && (int64_t)P.probs.size() == count &&
+  return P.device == device && P.epoch == g_policy_epoch.load() && (int64_t)P.probs.size() == count &&
          std::memcmp(P.probs.data(), probs, sizeof(gf2_problem) * (size_t)count) == 0;
 }
 
@@ -892,6 +1008,7 @@ gf2_status gf2_set_policy(int32_t policy) {
   if (policy < GF2_POLICY_FIXED || policy > GF2_POLICY_MODEL)
     return set_error(GF2_ERR_INVALID_ARG, "unknown policy %d", policy);
   g_policy.store(policy);
+  ++g_policy_epoch;
   return GF2_OK;
 }
 
@@ -911,6 +1028,20 @@ gf2_status gf2_autotune(int64_t m, int64_t k, int64_t n, double density, int32_t
   if (r != GF2_OK) return r;
   if (ms) std::copy(v.begin(), v.end(), ms);
   if (best) *best = argmin_allowed(v, false);
+  return GF2_OK;
+}
+
+gf2_status gf2_autotune_batch(int64_t m, int64_t k, int64_t n, double density, int32_t reps, float* ms,
+                              int32_t* best, int32_t* copies) {
+  g_err[0] = 0;
+  if (density < 0 || density > 1) return set_error(GF2_ERR_INVALID_ARG, "density must be in [0, 1]");
+  std::vector<float> v;
+  int R = 0;
+  gf2_status r = autotune_batch_shape(m, k, n, density, reps, v, R);
+  if (r != GF2_OK) return r;
+  if (ms) std::copy(v.begin(), v.end(), ms);
+  if (best) *best = argmin_allowed(v, true);
+  if (copies) *copies = R;
   return GF2_OK;
 }
 
@@ -943,12 +1074,14 @@ gf2_status gf2_autotune_load(const char* path) {
   if (!f.eof()) return set_error(GF2_ERR_INVALID_ARG, "%s: malformed (cache left unchanged)", path);
   std::lock_guard<std::mutex> g(g_tune_mu);
   for (auto& kv : loaded) g_tune[kv.first] = kv.second;
+  ++g_policy_epoch;
   return GF2_OK;
 }
 
 void gf2_autotune_clear(void) {
   std::lock_guard<std::mutex> g(g_tune_mu);
   g_tune.clear();
+  ++g_policy_epoch;
 }
 
 int32_t gf2_kernel_variants(int32_t kernel) {

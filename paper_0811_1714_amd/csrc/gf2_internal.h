@@ -60,6 +60,7 @@ bool model_predict(int64_t m, int64_t k, int64_t n, double density, float* out);
 bool model_available();
 gf2_status model_choose_batch(const std::vector<float>& feats_raw, const uint8_t* allowed_host, std::vector<int>& out);
 bool batch_allowed(int candidate);
+void bump_policy_epoch();   // invalidates cached batch plans after a policy or model change
 
 // ---- kernels (each .hip file owns its launches) ----
 // Products launched together with descriptors passed by value in the kernel arguments.
@@ -123,12 +124,30 @@ struct OView {
   uint64_t tail;       // mask for word wds-1 (padding bits written 0 or left unchanged)
 };
 gf2_status fill_zero(const OView& o, hipStream_t s);
+// Strassen-Winograd passes of one recursion node (``depth`` 0 = the root).
+struct PreOp {
+  int32_t kind;        // 0: S0..S3 from A's quadrants; 1: T0..T3 from B's
+  int32_t depth;
+  QView in[4];         // NW, NE, SW, SE
+  uint64_t* out[4];
+  int64_t ldo, R, Wd;
+};
+struct PostOp {
+  int32_t mode;        // OutMode for C
+  int32_t depth;
+  const uint64_t* P[7];
+  int64_t ldp;
+  OView c[4];          // C_NW, C_NE, C_SW, C_SE
+};
+// Many independent ops in one launch (device arrays); max_elems = largest op's word count.
+gf2_status fill_zero_multi(const OView* dev_ops, int n, int64_t max_elems, hipStream_t s);
+gf2_status strassen_pre_multi(const PreOp* dev_ops, int n, int64_t max_elems, hipStream_t s);
+gf2_status strassen_post_multi(const PostOp* dev_ops, int n, int64_t max_elems, hipStream_t s);
 gf2_status fill_random(uint64_t* p, int64_t nwords, uint64_t seed, double density, hipStream_t s);
 // Strassen-Winograd pre-additions (Algorithm 4): from the four quadrants NW, NE, SW, SE
 // of A (kind 0) produce S0..S3, of B (kind 1) produce T0..T3, over R x Wd words.
-gf2_status strassen_pre(int kind, const QView in[4], uint64_t* const out[4], int64_t ldo, int64_t R, int64_t Wd,
-                        hipStream_t s);
-// Post-additions: from P0..P6 (R0 x W0 words each, ld ldp) write the four quadrants of C.
-gf2_status strassen_post(const uint64_t* const P[7], int64_t ldp, const OView c[4], int out_mode, hipStream_t s);
+gf2_status strassen_pre(const PreOp& op, hipStream_t s);
+// Post-additions: from P0..P6 (ld ldp) write the four quadrants of C.
+gf2_status strassen_post(const PostOp& op, hipStream_t s);
 
 }  // namespace gf2

@@ -72,7 +72,7 @@ bool model_predict(int64_t m, int64_t k, int64_t n, double density, float* out) 
   if (g_model.empty()) return false;
   float x[4];
   model_features(m, k, n, density, x);
-  mlp_forward_host(g_model.data(), x, kNumCandidates, out);
+  mlp_forward_host(g_model.data(), x, 2 * kNumCandidates, out);
   return true;
 }
 
@@ -106,9 +106,11 @@ gf2_status model_choose_batch(const std::vector<float>& feats_raw, const uint8_t
       x[4 * b + i] = (float)((raw[i] - g_norm[i]) / (g_norm[4 + i] != 0 ? g_norm[4 + i] : 1.0f));
   }
   // One allocation: X, Y, acts, allowed, out.
-  const size_t fX = nb * 4, fY = nb * kNumCandidates, fA = 3 * nb * 64;
+  const int NO = 2 * kNumCandidates;   // batch outputs are the second half
+  const size_t fX = nb * 4, fY = nb * NO, fA = 3 * nb * 64;
   const size_t bytes = (fX + fY + fA) * sizeof(float) + 64 + nb * sizeof(int32_t);
   char* buf = nullptr;
+  static_assert(2 * kNumCandidates <= 64, "allowed mask area");
   if (hipMalloc(&buf, bytes) != hipSuccess) return set_error(GF2_ERR_ALLOC, "hipMalloc for model inference failed");
   float* dX = reinterpret_cast<float*>(buf);
   float* dY = dX + fX;
@@ -117,12 +119,14 @@ gf2_status model_choose_batch(const std::vector<float>& feats_raw, const uint8_t
   int32_t* dOut = reinterpret_cast<int32_t*>(dAllowed + 64);
   std::vector<int32_t> host_out(nb);
   r = hip_check(hipMemcpy(dX, x.data(), fX * sizeof(float), hipMemcpyHostToDevice), "hipMemcpy");
-  if (r == GF2_OK) r = hip_check(hipMemcpy(dAllowed, allowed_host, kNumCandidates, hipMemcpyHostToDevice), "hipMemcpy");
-  if (r == GF2_OK) r = mlp_forward(g_model_dev, dX, nb, kNumCandidates, dY, dA, nullptr);
-  if (r == GF2_OK) r = mlp_argmin(dY, nb, kNumCandidates, dAllowed, dOut, nullptr);
+  std::vector<uint8_t> mask(NO, 0);
+  for (int c = 0; c < kNumCandidates; ++c) mask[kNumCandidates + c] = allowed_host[c];
+  if (r == GF2_OK) r = hip_check(hipMemcpy(dAllowed, mask.data(), NO, hipMemcpyHostToDevice), "hipMemcpy");
+  if (r == GF2_OK) r = mlp_forward(g_model_dev, dX, nb, NO, dY, dA, nullptr);
+  if (r == GF2_OK) r = mlp_argmin(dY, nb, NO, dAllowed, dOut, nullptr);
   if (r == GF2_OK) r = hip_check(hipMemcpy(host_out.data(), dOut, nb * sizeof(int32_t), hipMemcpyDeviceToHost), "hipMemcpy");
   (void)hipFree(buf);
-  for (int64_t b = 0; b < nb; ++b) out[b] = host_out[b];
+  for (int64_t b = 0; b < nb; ++b) out[b] = host_out[b] >= kNumCandidates ? host_out[b] - kNumCandidates : -1;
   return r;
 }
 
@@ -139,20 +143,20 @@ extern "C" {
 
 int32_t gf2_num_candidates(void) { return kNumCandidates; }
 
-int64_t gf2_mlp_param_count(void) { return mlp_param_count(kNumCandidates); }
-int64_t gf2_mlp_scratch_floats(int64_t batch) { return batch < 0 ? 0 : mlp_scratch_floats(batch, kNumCandidates); }
+int64_t gf2_mlp_param_count(void) { return mlp_param_count(2 * kNumCandidates); }
+int64_t gf2_mlp_scratch_floats(int64_t batch) { return batch < 0 ? 0 : mlp_scratch_floats(batch, 2 * kNumCandidates); }
 
 gf2_status gf2_mlp_forward(const float* params, const float* X, int64_t batch, float* Y, float* acts, void* stream) {
   if (batch < 0 || (batch > 0 && (!params || !X || !Y || !acts)))
     return set_error(GF2_ERR_INVALID_ARG, "gf2_mlp_forward: bad arguments");
-  return mlp_forward(params, X, batch, kNumCandidates, Y, acts, static_cast<hipStream_t>(stream));
+  return mlp_forward(params, X, batch, 2 * kNumCandidates, Y, acts, static_cast<hipStream_t>(stream));
 }
 
 gf2_status gf2_mlp_backward(const float* params, const float* X, int64_t batch, const float* acts, const float* Y,
                             const float* T, const float* M, float* grads, float* scratch, float* loss, void* stream) {
   if (batch < 0 || !params || !grads || !scratch || (batch > 0 && (!X || !acts || !Y || !T || !M)))
     return set_error(GF2_ERR_INVALID_ARG, "gf2_mlp_backward: bad arguments");
-  return mlp_backward(params, X, batch, kNumCandidates, acts, Y, T, M, grads, scratch, loss,
+  return mlp_backward(params, X, batch, 2 * kNumCandidates, acts, Y, T, M, grads, scratch, loss,
                       static_cast<hipStream_t>(stream));
 }
 
@@ -165,10 +169,11 @@ gf2_status gf2_mlp_adam(float* params, const float* grads, float* m, float* v, i
 
 gf2_status gf2_mlp_argmin(const float* Y, int64_t batch, const uint8_t* allowed, int32_t* out, void* stream) {
   if (batch < 0 || (batch > 0 && (!Y || !out))) return set_error(GF2_ERR_INVALID_ARG, "gf2_mlp_argmin: bad arguments");
-  return mlp_argmin(Y, batch, kNumCandidates, allowed, out, static_cast<hipStream_t>(stream));
+  return mlp_argmin(Y, batch, 2 * kNumCandidates, allowed, out, static_cast<hipStream_t>(stream));
 }
 
 gf2_status gf2_set_model(const float* params, int64_t count, const float* norm) {
+  bump_policy_epoch();
   std::lock_guard<std::mutex> g(g_model_mu);
   if (g_model_dev) {
     (void)hipFree(g_model_dev);
@@ -179,9 +184,9 @@ gf2_status gf2_set_model(const float* params, int64_t count, const float* norm) 
     g_model.clear();
     return GF2_OK;
   }
-  if (count != mlp_param_count(kNumCandidates))
+  if (count != mlp_param_count(2 * kNumCandidates))
     return set_error(GF2_ERR_INVALID_ARG, "model has %lld parameters, expected %lld", (long long)count,
-                     (long long)mlp_param_count(kNumCandidates));
+                     (long long)mlp_param_count(2 * kNumCandidates));
   g_model.assign(params, params + count);
   for (int i = 0; i < 8; ++i) g_norm[i] = norm ? norm[i] : (i < 4 ? 0.f : 1.f);
   return GF2_OK;

@@ -31,71 +31,87 @@ __global__ void fill_zero_kernel(OView o) {
   }
 }
 
-struct PreArgs {
-  QView in[4];          // NW, NE, SW, SE
-  uint64_t* out[4];     // S0..S3 or T0..T3
-  int64_t ldo, R, Wd;
-};
-
 // kind 0 (A):  S0 = SW+SE, S1 = S0+NW, S2 = NW+SW, S3 = NE+S1
 // kind 1 (B):  T0 = NE+NW, T1 = SE+T0, T2 = SE+NE, T3 = T1+SW
-template <int KIND>
-__global__ void strassen_pre_kernel(PreArgs a) {
-  const int64_t total = a.R * a.Wd;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t r = i / a.Wd, w = i - r * a.Wd;
-    const uint64_t nw = qload(a.in[0], r, w), ne = qload(a.in[1], r, w);
-    const uint64_t sw = qload(a.in[2], r, w), se = qload(a.in[3], r, w);
-    uint64_t o0, o1, o2, o3;
-    if (KIND == 0) {
-      o0 = sw ^ se;
-      o1 = o0 ^ nw;
-      o2 = nw ^ sw;
-      o3 = ne ^ o1;
-    } else {
-      o0 = ne ^ nw;
-      o1 = se ^ o0;
-      o2 = se ^ ne;
-      o3 = o1 ^ sw;
-    }
-    const int64_t off = r * a.ldo + w;
-    a.out[0][off] = o0;
-    a.out[1][off] = o1;
-    a.out[2][off] = o2;
-    a.out[3][off] = o3;
+__device__ __forceinline__ void pre_element(const PreOp& a, int64_t i) {
+  const int64_t r = i / a.Wd, w = i - r * a.Wd;
+  const uint64_t nw = qload(a.in[0], r, w), ne = qload(a.in[1], r, w);
+  const uint64_t sw = qload(a.in[2], r, w), se = qload(a.in[3], r, w);
+  uint64_t o0, o1, o2, o3;
+  if (a.kind == 0) {
+    o0 = sw ^ se;
+    o1 = o0 ^ nw;
+    o2 = nw ^ sw;
+    o3 = ne ^ o1;
+  } else {
+    o0 = ne ^ nw;
+    o1 = se ^ o0;
+    o2 = se ^ ne;
+    o3 = o1 ^ sw;
   }
+  const int64_t off = r * a.ldo + w;
+  a.out[0][off] = o0;
+  a.out[1][off] = o1;
+  a.out[2][off] = o2;
+  a.out[3][off] = o3;
 }
 
-struct PostArgs {
-  const uint64_t* P[7];
-  int64_t ldp;
-  OView c[4];           // C_NW, C_NE, C_SW, C_SE (their written regions)
-  int mode;
-};
+__global__ void strassen_pre_kernel(PreOp a) {
+  const int64_t total = a.R * a.Wd;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x)
+    pre_element(a, i);
+}
+
+__global__ void strassen_pre_multi_kernel(const PreOp* __restrict__ ops) {
+  const PreOp a = ops[blockIdx.y];
+  const int64_t total = a.R * a.Wd;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x)
+    pre_element(a, i);
+}
 
 // U0 = P0+P1, U1 = P0+P5, U2 = U1+P6, U3 = U1+P4, U4 = U3+P2, U5 = U2+P3, U6 = U2+P4;
 // C_NW = U0, C_NE = U4, C_SW = U5, C_SE = U6.  The grid covers C_NW's region, which
 // contains the other three (top/left halves are the larger ones).
-__global__ void strassen_post_kernel(PostArgs a) {
-  const int64_t R = a.c[0].rows, Wd = a.c[0].wds, total = R * Wd;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t r = i / Wd, w = i - r * Wd;
-    const int64_t off = r * a.ldp + w;
-    const bool ne = r < a.c[1].rows && w < a.c[1].wds;
-    const bool sw = r < a.c[2].rows && w < a.c[2].wds;
-    const bool se = r < a.c[3].rows && w < a.c[3].wds;
-    const uint64_t p0 = a.P[0][off];
-    owrite(a.c[0], r, w, p0 ^ a.P[1][off], a.mode);
-    if (ne || sw || se) {
-      const uint64_t u1 = p0 ^ a.P[5][off];
-      const uint64_t p4 = (ne || se) ? a.P[4][off] : 0;
-      if (ne) owrite(a.c[1], r, w, u1 ^ p4 ^ a.P[2][off], a.mode);
-      if (sw || se) {
-        const uint64_t u2 = u1 ^ a.P[6][off];
-        if (sw) owrite(a.c[2], r, w, u2 ^ a.P[3][off], a.mode);
-        if (se) owrite(a.c[3], r, w, u2 ^ p4, a.mode);
-      }
+__device__ __forceinline__ void post_element(const PostOp& a, int64_t i) {
+  const int64_t Wd = a.c[0].wds;
+  const int64_t r = i / Wd, w = i - r * Wd;
+  const int64_t off = r * a.ldp + w;
+  const bool ne = r < a.c[1].rows && w < a.c[1].wds;
+  const bool sw = r < a.c[2].rows && w < a.c[2].wds;
+  const bool se = r < a.c[3].rows && w < a.c[3].wds;
+  const uint64_t p0 = a.P[0][off];
+  owrite(a.c[0], r, w, p0 ^ a.P[1][off], a.mode);
+  if (ne || sw || se) {
+    const uint64_t u1 = p0 ^ a.P[5][off];
+    const uint64_t p4 = (ne || se) ? a.P[4][off] : 0;
+    if (ne) owrite(a.c[1], r, w, u1 ^ p4 ^ a.P[2][off], a.mode);
+    if (sw || se) {
+      const uint64_t u2 = u1 ^ a.P[6][off];
+      if (sw) owrite(a.c[2], r, w, u2 ^ a.P[3][off], a.mode);
+      if (se) owrite(a.c[3], r, w, u2 ^ p4, a.mode);
     }
+  }
+}
+
+__global__ void strassen_post_kernel(PostOp a) {
+  const int64_t total = a.c[0].rows * a.c[0].wds;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x)
+    post_element(a, i);
+}
+
+__global__ void strassen_post_multi_kernel(const PostOp* __restrict__ ops) {
+  const PostOp a = ops[blockIdx.y];
+  const int64_t total = a.c[0].rows * a.c[0].wds;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x)
+    post_element(a, i);
+}
+
+__global__ void fill_zero_multi_kernel(const OView* __restrict__ ops) {
+  const OView o = ops[blockIdx.y];
+  const int64_t total = o.rows * o.wds;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / o.wds, w = i - r * o.wds;
+    o.p[r * o.ld + w] = 0;
   }
 }
 
@@ -114,29 +130,44 @@ gf2_status fill_zero(const OView& o, hipStream_t s) {
   return hip_check(hipGetLastError(), "fill_zero launch");
 }
 
-gf2_status strassen_pre(int kind, const QView in[4], uint64_t* const out[4], int64_t ldo, int64_t R, int64_t Wd,
-                        hipStream_t s) {
-  if (R <= 0 || Wd <= 0) return GF2_OK;
-  PreArgs a;
-  for (int i = 0; i < 4; ++i) { a.in[i] = in[i]; a.out[i] = out[i]; }
-  a.ldo = ldo; a.R = R; a.Wd = Wd;
-  TraceScope trace(GF2_TRACE_PRE, 1, 8.0 * 8 * R * Wd, s);   // 4 quadrants in, 4 out
-  if (kind == 0) hipLaunchKernelGGL(strassen_pre_kernel<0>, dim3(grid_for(R * Wd)), dim3(kThreads), 0, s, a);
-  else hipLaunchKernelGGL(strassen_pre_kernel<1>, dim3(grid_for(R * Wd)), dim3(kThreads), 0, s, a);
+gf2_status strassen_pre(const PreOp& op, hipStream_t s) {
+  if (op.R <= 0 || op.Wd <= 0) return GF2_OK;
+  TraceScope trace(GF2_TRACE_PRE, 1, 8.0 * 8 * op.R * op.Wd, s);   // 4 quadrants in, 4 out
+  hipLaunchKernelGGL(strassen_pre_kernel, dim3(grid_for(op.R * op.Wd)), dim3(kThreads), 0, s, op);
   return hip_check(hipGetLastError(), "strassen_pre launch");
 }
 
-gf2_status strassen_post(const uint64_t* const P[7], int64_t ldp, const OView c[4], int out_mode, hipStream_t s) {
-  PostArgs a;
-  for (int i = 0; i < 7; ++i) a.P[i] = P[i];
-  for (int i = 0; i < 4; ++i) a.c[i] = c[i];
-  a.ldp = ldp;
-  a.mode = out_mode;
-  const int64_t total = c[0].rows * c[0].wds;
+gf2_status strassen_post(const PostOp& op, hipStream_t s) {
+  const int64_t total = op.c[0].rows * op.c[0].wds;
   if (total <= 0) return GF2_OK;
   TraceScope trace(GF2_TRACE_POST, 1, 8.0 * 11 * total, s);   // 7 products in, 4 quadrants out
-  hipLaunchKernelGGL(strassen_post_kernel, dim3(grid_for(total)), dim3(kThreads), 0, s, a);
+  hipLaunchKernelGGL(strassen_post_kernel, dim3(grid_for(total)), dim3(kThreads), 0, s, op);
   return hip_check(hipGetLastError(), "strassen_post launch");
+}
+
+// Multi-op launches: blockIdx.y selects the op; x blocks stride over its words.
+unsigned multi_x(int64_t max_elems, int n) {
+  int64_t b = (max_elems + kThreads - 1) / kThreads;
+  const int64_t cap = n >= 64 ? 16 : 256 * 8 / (n > 0 ? n : 1);
+  return (unsigned)(b < 1 ? 1 : (b > cap ? cap : b));
+}
+
+gf2_status fill_zero_multi(const OView* dev_ops, int n, int64_t max_elems, hipStream_t s) {
+  if (n <= 0 || max_elems <= 0) return GF2_OK;
+  hipLaunchKernelGGL(fill_zero_multi_kernel, dim3(multi_x(max_elems, n), n), dim3(kThreads), 0, s, dev_ops);
+  return hip_check(hipGetLastError(), "fill_zero_multi launch");
+}
+
+gf2_status strassen_pre_multi(const PreOp* dev_ops, int n, int64_t max_elems, hipStream_t s) {
+  if (n <= 0 || max_elems <= 0) return GF2_OK;
+  hipLaunchKernelGGL(strassen_pre_multi_kernel, dim3(multi_x(max_elems, n), n), dim3(kThreads), 0, s, dev_ops);
+  return hip_check(hipGetLastError(), "strassen_pre_multi launch");
+}
+
+gf2_status strassen_post_multi(const PostOp* dev_ops, int n, int64_t max_elems, hipStream_t s) {
+  if (n <= 0 || max_elems <= 0) return GF2_OK;
+  hipLaunchKernelGGL(strassen_post_multi_kernel, dim3(multi_x(max_elems, n), n), dim3(kThreads), 0, s, dev_ops);
+  return hip_check(hipGetLastError(), "strassen_post_multi launch");
 }
 
 }  // namespace gf2

@@ -1,6 +1,8 @@
 """Timing dataset for the schedule model: every candidate schedule timed by the library's
-autotuner (gf2_autotune) on products with m, k, n log-uniform in [64, 4096) and density
-log-uniform in [0.01, 0.5] (the batched workload's shape law).
+autotuner on products with m, k, n log-uniform in [64, 4096) and density log-uniform in
+[0.01, 0.5] (the batched workload's shape law).  Columns 0..S-1 of ``*_ms`` are the
+isolated latency (gf2_autotune), columns S..2S-1 the per-product time inside a batch of
+copies (gf2_autotune_batch).
 
     python -m paper_0811_1714_amd.tune.timings --count 20000 --heldout 500 --out timings.npz
 """
@@ -24,13 +26,16 @@ def shapes(seed, count, tag):
 
 
 def collect(dims, dens, reps, label, budget_s=None):
+    """Isolated latency (gf2_autotune) and per-product time inside a batch of copies
+    (gf2_autotune_batch) of every candidate, for every shape."""
     import paper_0811_1714_amd as g
     S = g.num_candidates()
-    ms = np.full((len(dims), S), -1.0, dtype=np.float32)
+    ms = np.full((len(dims), 2 * S), -1.0, dtype=np.float32)
     t0 = time.time()
     done = len(dims)
     for i, ((m, k, n), p) in enumerate(zip(dims, dens)):
-        ms[i], _ = g.autotune(int(m), int(k), int(n), float(p), reps)
+        ms[i, :S], _ = g.autotune(int(m), int(k), int(n), float(p), reps)
+        ms[i, S:], _, _ = g.autotune_batch(int(m), int(k), int(n), float(p), reps)
         if (i + 1) % 500 == 0:
             print(f"{label}: {i + 1}/{len(dims)} shapes timed, {time.time() - t0:.0f} s", flush=True)
         if budget_s is not None and time.time() - t0 > budget_s:

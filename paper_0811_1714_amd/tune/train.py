@@ -2,9 +2,10 @@
 gf2_mlp_backward, gf2_mlp_adam), from a timing dataset written by ``tune.timings``.
 
 Inputs: (log2 m, log2 k, log2 n, density), standardised.  Targets: log of each
-candidate's median runtime (ms), standardised over all observed entries; candidates that
-could not run are masked out of the loss.  Evaluation: schedule regret on the held-out
-shapes, t(chosen) / t(fastest) - 1, for the model and for the fixed heuristic.
+candidate's median runtime (ms), alone (first S outputs) and per product inside a batch
+(last S), each half standardised on its own (argmin within a half is unchanged);
+candidates that could not run are masked out of the loss.  Evaluation: schedule regret on
+the held-out shapes, t(chosen) / t(fastest) - 1, for the model and the fixed heuristic.
 
     python -m paper_0811_1714_amd.tune.train --data timings.npz --out model.npz
 """
@@ -99,19 +100,23 @@ def main():
     import paper_0811_1714_amd as g
     g.lib()
     S = g.num_candidates()
+    NO = 2 * S
     d = np.load(args.data)
     Xtr_raw, Xho_raw = features(d["train_dims"], d["train_density"]), features(d["heldout_dims"], d["heldout_density"])
     ms_tr, ms_ho = d["train_ms"].astype(np.float64), d["heldout_ms"].astype(np.float64)
     mean, std = Xtr_raw.mean(axis=0), Xtr_raw.std(axis=0) + 1e-9
     Mtr = (ms_tr > 0).astype(np.float32)
     logt = np.where(ms_tr > 0, np.log(np.maximum(ms_tr, 1e-9)), 0.0)
-    tmean = float(logt[Mtr > 0].mean()); tstd = float(logt[Mtr > 0].std() + 1e-9)
+    tmean, tstd = np.zeros(NO), np.ones(NO)
+    for h in (slice(0, S), slice(S, NO)):
+        v = logt[:, h][Mtr[:, h] > 0]
+        tmean[h], tstd[h] = v.mean(), v.std() + 1e-9
     Ttr = ((logt - tmean) / tstd * Mtr).astype(np.float32)
     Xtr = ((Xtr_raw - mean) / std).astype(np.float32)
     Xho = ((Xho_raw - mean) / std).astype(np.float32)
 
-    tr = Trainer(g, S, args.batch)
-    tr.params.copy_(torch.from_numpy(init_params(S, args.seed)))
+    tr = Trainer(g, NO, args.batch)
+    tr.params.copy_(torch.from_numpy(init_params(NO, args.seed)))
     rng = np.random.default_rng(args.seed)
     n = len(Xtr)
     history = []
@@ -133,17 +138,19 @@ def main():
     pred_ho = tr.predict(Xho)
     allowed = np.array([g.candidate(i).kernel == g.KERNEL_M4RM and 1 <= g.candidate(i).variant <= 4
                         for i in range(S)])
-    choice_all = np.argmin(pred_ho, axis=1)
-    choice_batch = np.where(allowed, pred_ho, np.inf).argmin(axis=1)
+    lat_ho, thr_ho = ms_ho[:, :S], ms_ho[:, S:]
+    choice_lat = np.argmin(pred_ho[:, :S], axis=1)
+    choice_thr = np.where(allowed, pred_ho[:, S:], np.inf).argmin(axis=1)
     g.set_policy(g.POLICY_FIXED)
     heur = np.array([g.choose_schedule(int(m), int(k), int(nn), batch=True) for m, k, nn in d["heldout_dims"]])
-    ms_ho_batch = np.where(allowed[None, :], ms_ho, -1.0)
+    thr_allowed = np.where(allowed[None, :], thr_ho, -1.0)
     report = {
         "train_shapes": int(n), "heldout_shapes": int(len(Xho)), "epochs": args.epochs,
         "final_train_mse": history[-1][1],
-        "regret_model_all_candidates": summarize(regret(ms_ho, choice_all)),
-        "regret_model_batch_candidates": summarize(regret(ms_ho_batch, choice_batch)),
-        "regret_fixed_heuristic_batch_candidates": summarize(regret(ms_ho_batch, heur)),
+        "regret_latency_model": summarize(regret(lat_ho, choice_lat)),
+        "regret_latency_fixed_heuristic": summarize(regret(lat_ho, heur)),
+        "regret_batch_model": summarize(regret(thr_allowed, choice_thr)),
+        "regret_batch_fixed_heuristic": summarize(regret(thr_allowed, heur)),
     }
     np.savez(args.out, params=params, norm=norm, target_mean=tmean, target_std=tstd,
              history=np.array(history), report=json.dumps(report))

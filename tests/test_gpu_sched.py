@@ -31,7 +31,7 @@ def split_params(flat, S):
 
 def test_mlp_forward_backward_adam_match_float64_reference(g):
     import torch
-    S = g.num_candidates()
+    S = 2 * g.num_candidates()          # latency head and batch-throughput head
     P = g.mlp_param_count()
     assert P == 4 * 64 + 64 + 2 * (64 * 64 + 64) + 64 * S + S
     rng = np.random.default_rng(0)
@@ -69,11 +69,11 @@ def test_mlp_forward_backward_adam_match_float64_reference(g):
     np.testing.assert_allclose(dp.cpu().numpy(), newp[0], rtol=1e-5, atol=1e-6)
     # argmin with a mask
     allowed = torch.zeros(S, dtype=torch.uint8, device="cuda")
-    allowed[[1, 3, 5]] = 1
+    allowed[[1, 3, 5, 13]] = 1
     out = torch.empty(batch, dtype=torch.int32, device="cuda")
     g.mlp_argmin(dY, out, allowed)
     y = dY.cpu().numpy()
-    sub = np.array([1, 3, 5])
+    sub = np.array([1, 3, 5, 13])
     assert np.array_equal(out.cpu().numpy(), sub[np.argmin(y[:, sub], axis=1)])
 
 
@@ -82,6 +82,8 @@ def test_autotune_and_policies_keep_bits(g):
     ms, best = g.autotune(700, 900, 1100, density=0.3, reps=2)
     assert ms.shape == (g.num_candidates(),) and 0 <= best < ms.size and ms[best] > 0
     assert ms[best] == ms[ms > 0].min()
+    mb, bb, copies = g.autotune_batch(300, 500, 700, density=0.5, reps=2)
+    assert copies >= 2 and 0 <= bb < mb.size and mb[bb] > 0 and (mb > 0).sum() >= 7
     try:
         base = run_and_check(g, 700, 900, 1100, seed=41)
         g.set_policy(g.POLICY_AUTOTUNE)
