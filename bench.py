@@ -119,8 +119,8 @@ def sweep(g):
         B = synth.uniform(1, synth.TAG_B, n, n)
         dA, dB = to_dev(A), to_dev(B)
         dC = torch.empty_like(dA)
-        for cutoff in (0, n // 2, n // 4):
-            if cutoff and cutoff < 2048 or (cutoff == n // 2 and n > 8192):
+        for cutoff in (0, n // 2, n // 4, n // 8):
+            if cutoff and cutoff < 2048:
                 continue
             for v in SWEEP_VARIANTS or range(g.kernel_variants(g.KERNEL_M4RM)):
                 s = g.Schedule(g.KERNEL_M4RM, v, cutoff, 1)

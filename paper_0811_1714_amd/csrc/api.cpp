@@ -125,32 +125,98 @@ gf2_schedule g_override{};
 
 uint64_t tail_of(int64_t cols) { return (cols & 63) ? ((1ull << (cols & 63)) - 1) : ~0ull; }
 
-// Default schedule for a shape (the fixed heuristic, used when nothing better is known):
-// the tallest M4RM tile that still gives every compute unit work, two Strassen-Winograd
-// levels once the smallest dimension reaches 8192, and k split when there are too few
-// C tiles to fill 256 compute units.
 int64_t tiles_for(int64_t m, int64_t n, int v) {
   const int64_t bm = m4rm_tile_rows(v), tw = m4rm_tile_words(v);
   return ((m + bm - 1) / bm) * ((words(n) + tw - 1) / tw);
 }
 
+bool splittable(int64_t m, int64_t k, int64_t n, int64_t cutoff);
+
+int compute_units() {
+  static std::atomic<int> cached{0};
+  int c = cached.load();
+  if (c == 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c <= 0)
+      c = 256;
+    cached.store(c);
+  }
+  return c;
+}
+
+// Predicted time (ms) of an M4RM schedule on MI355X.  A tile of the 16-wave two-table
+// kernel costs, per 16-row phase of B, a fixed part (table build, barrier, B loads), a
+// part per tile row (lookups) and a cache-miss part that grows with the leaf's B beyond
+// 8 MiB; tiles of one launch run in rounds of one per compute unit.  Strassen-Winograd
+// passes move about (2mk + 2kn + 2.75mn)/8 bytes per node.  The constants were fitted to
+// square products of 8192, 16384 and 32768 at every tile height and depth.
+struct CostAcc {
+  double tile_ms = 0, add_bytes = 0;
+  int64_t tiles = 0;
+};
+constexpr double kPhaseMs = 5.75e-4, kRowPhaseMs = 6.5e-7, kMissMs = 1.25e-4, kAddBytesPerMs = 2.0e9;
+
+void cost_walk(int64_t m, int64_t k, int64_t n, int64_t cutoff, int v, CostAcc& a) {
+  if (!splittable(m, k, n, cutoff)) {
+    const int64_t t = tiles_for(m, n, v);
+    const double bbytes = (double)k * (double)n / 8.0;
+    const double miss = bbytes > 8.0 * (1 << 20) ? kMissMs * std::log2(bbytes / (8.0 * (1 << 20))) : 0.0;
+    a.tiles += t;
+    a.tile_ms += (double)t * (double)((k + 15) / 16) * (kPhaseMs + kRowPhaseMs * m4rm_tile_rows(v) + miss);
+    return;
+  }
+  a.add_bytes += (2.0 * m * k + 2.0 * k * n + 2.75 * m * n) / 8.0;
+  const int64_t m0 = (m + 1) / 2, m1 = m - m0;
+  const int64_t k0 = 64 * ((words(k) + 1) / 2), k1 = k - k0;
+  const int64_t n0 = 64 * ((words(n) + 1) / 2), n1 = n - n0;
+  cost_walk(m0, k0, n0, cutoff, v, a);   // P0, P4, P5, P6
+  cost_walk(m0, k0, n0, cutoff, v, a);
+  cost_walk(m0, k0, n0, cutoff, v, a);
+  cost_walk(m0, k0, n0, cutoff, v, a);
+  cost_walk(m0, k1, n0, cutoff, v, a);   // P1
+  cost_walk(m0, k1, n1, cutoff, v, a);   // P2
+  cost_walk(m1, k1, n0, cutoff, v, a);   // P3
+}
+
+double predicted_ms(int64_t m, int64_t k, int64_t n, int64_t cutoff, int v) {
+  CostAcc a;
+  cost_walk(m, k, n, cutoff, v, a);
+  if (a.tiles == 0) return 0;
+  const int64_t cus = compute_units();
+  const double rounds = (double)((a.tiles + cus - 1) / cus);
+  return rounds * a.tile_ms / (double)a.tiles + a.add_bytes / kAddBytesPerMs;
+}
+
+// Default schedule for a shape (the fixed heuristic, used when nothing better is known).
+// Large products (smallest dimension >= 4096): the M4RM tile height and Strassen-Winograd
+// depth with the lowest predicted time.  Smaller ones: the tallest tile that still gives
+// every compute unit work, and k split when there are too few C tiles to fill them.
 gf2_schedule default_schedule(int64_t m, int64_t k, int64_t n) {
   gf2_schedule s{};
   s.kernel = GF2_KERNEL_M4RM;
+  s.splitk = 1;
   const int64_t mn = m < n ? (m < k ? m : k) : (n < k ? n : k);
-  s.cutoff = mn >= 8192 ? (int32_t)(mn / 4) : 0;
-  const int64_t lm = s.cutoff ? (m + 3) / 4 : m, ln = s.cutoff ? (n + 3) / 4 : n;
-  const int64_t leaves = s.cutoff ? 49 : 1;
-  const int order[] = {0, 1, 2, 3};
+  if (mn >= 4096) {
+    double best = -1;
+    for (int64_t cutoff : {int64_t(0), mn / 2, mn / 4, mn / 8}) {
+      if (cutoff && cutoff < 2048) continue;
+      for (int v : {0, 10, 1, 2, 3}) {
+        if (v >= m4rm_num_variants()) continue;
+        const double t = predicted_ms(m, k, n, cutoff, v);
+        if (best < 0 || t < best) { best = t; s.variant = v; s.cutoff = (int32_t)cutoff; }
+      }
+    }
+    return s;
+  }
   int v = 3;
-  for (int vi : order) {
-    if (tiles_for(lm, ln, vi) * leaves >= 512) { v = vi; break; }
+  for (int vi : {0, 1, 2, 3}) {
+    if (tiles_for(m, n, vi) >= 512) { v = vi; break; }
   }
   s.variant = v;
-  const int64_t tiles = tiles_for(lm, ln, v) * leaves;
+  const int64_t tiles = tiles_for(m, n, v);
   int sk = 1;
-  if (!s.cutoff)
-    while (tiles * sk < 512 && k / (64 * (sk * 2)) >= 16 && sk * 2 <= kMaxGroup) sk *= 2;
+  while (tiles * sk < 512 && k / (64 * (sk * 2)) >= 16 && sk * 2 <= kMaxGroup) sk *= 2;
   s.splitk = sk;
   return s;
 }
@@ -407,11 +473,25 @@ gf2_status execute(uint64_t* C, int64_t ldc, const uint64_t* A, int64_t lda, con
   uint64_t* scratch = ws ? ws + pp.st.ws_words : nullptr;
   if (need > 0) lease.used();
   if (!pp.st.leaves.empty()) {
-    for (const PreOp& p : pp.st.pre)
-      if ((r = strassen_pre(p, st)) != GF2_OK) return r;
+    // Passes of one recursion depth are independent: pre-additions run depth by depth from
+    // the root down, post-additions from the deepest level up, each depth in few launches.
+    std::vector<PreOp> pre = pp.st.pre;
+    std::vector<PostOp> post = pp.st.post;
+    std::stable_sort(pre.begin(), pre.end(), [](const PreOp& a, const PreOp& b) { return a.depth < b.depth; });
+    std::stable_sort(post.begin(), post.end(), [](const PostOp& a, const PostOp& b) { return a.depth > b.depth; });
+    for (size_t i = 0; i < pre.size();) {
+      size_t j = i;
+      while (j < pre.size() && pre[j].depth == pre[i].depth) ++j;
+      if ((r = strassen_pre_ops(pre.data() + i, (int)(j - i), st)) != GF2_OK) return r;
+      i = j;
+    }
     if ((r = run_base(s, pp.st.leaves, scratch, st)) != GF2_OK) return r;
-    for (const PostOp& p : pp.st.post)   // children were pushed before their parent
-      if ((r = strassen_post(p, st)) != GF2_OK) return r;
+    for (size_t i = 0; i < post.size();) {
+      size_t j = i;
+      while (j < post.size() && post[j].depth == post[i].depth) ++j;
+      if ((r = strassen_post_ops(post.data() + i, (int)(j - i), st)) != GF2_OK) return r;
+      i = j;
+    }
     return GF2_OK;
   }
   if (s.splitk > 1 && words(k) > 1 && !accumulate)

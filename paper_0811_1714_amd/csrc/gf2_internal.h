@@ -124,7 +124,10 @@ struct OView {
   uint64_t tail;       // mask for word wds-1 (padding bits written 0 or left unchanged)
 };
 gf2_status fill_zero(const OView& o, hipStream_t s);
-// Strassen-Winograd passes of one recursion node (``depth`` 0 = the root).
+// Strassen-Winograd passes of one recursion node (``depth`` 0 = the root), Algorithm 4.
+// Pre-additions: from the quadrants NW, NE, SW, SE of A (kind 0) produce S0..S3, of B
+// (kind 1) T0..T3, over R x Wd words.  Post-additions: from P0..P6 (ld ldp) write the
+// four quadrants of C.
 struct PreOp {
   int32_t kind;        // 0: S0..S3 from A's quadrants; 1: T0..T3 from B's
   int32_t depth;
@@ -143,11 +146,11 @@ struct PostOp {
 gf2_status fill_zero_multi(const OView* dev_ops, int n, int64_t max_elems, hipStream_t s);
 gf2_status strassen_pre_multi(const PreOp* dev_ops, int n, int64_t max_elems, hipStream_t s);
 gf2_status strassen_post_multi(const PostOp* dev_ops, int n, int64_t max_elems, hipStream_t s);
+// Host arrays of ops that may run concurrently (one recursion depth), launched kArgOps at
+// a time with the ops as kernel arguments.
+constexpr int kArgOps = 16;
+gf2_status strassen_pre_ops(const PreOp* ops, int n, hipStream_t s);
+gf2_status strassen_post_ops(const PostOp* ops, int n, hipStream_t s);
 gf2_status fill_random(uint64_t* p, int64_t nwords, uint64_t seed, double density, hipStream_t s);
-// Strassen-Winograd pre-additions (Algorithm 4): from the four quadrants NW, NE, SW, SE
-// of A (kind 0) produce S0..S3, of B (kind 1) produce T0..T3, over R x Wd words.
-gf2_status strassen_pre(const PreOp& op, hipStream_t s);
-// Post-additions: from P0..P6 (ld ldp) write the four quadrants of C.
-gf2_status strassen_post(const PostOp& op, hipStream_t s);
 
 }  // namespace gf2

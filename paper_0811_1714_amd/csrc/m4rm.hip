@@ -247,6 +247,9 @@ __device__ __forceinline__ void m4rm_tile_any(const MulDesc& d, int tm, int tn, 
 // one v_bitop3 folds both lookups of a row into its accumulator
 // ("AddTwoRowsFromTable").  Eight rows per lookup instruction (8 lanes x 16 B per
 // 128 B half-entry).  Halving the tile width doubles the rows that share each table.
+// Rows of odd 8-lane groups look up the two tables in the opposite order, so every
+// 16 lanes of a lookup instruction cover both halves of the 64 LDS banks (table 0 in
+// banks 0-31, table 1 in banks 32-63) instead of contending for one half.
 constexpr int T2_WORDS = 16;                // 1024 columns per tile
 constexpr int PB = 2 * KB;                  // rows of B per phase
 
@@ -280,7 +283,11 @@ __device__ __forceinline__ void m4rm2_tile(const MulDesc& d, int tm, int tn, cha
   // A: dword gd of a row holds the indices of phases 2gd (bytes 0, 1) and 2gd+1 (bytes 2, 3).
   const __amdgpu_buffer_rsrc_t ra =
       make_rsrc(d.A + row0 * d.lda, rows_here > 0 ? (int64_t)(rows_here - 1) * lda_b + 4 * kdw : 0);
-  const uint32_t lb0 = (uint32_t)l8 * 16u, lb1 = 128u + (uint32_t)l8 * 16u;
+  // Odd 8-lane groups read table 1 first: their A dwords get bytes swapped in pairs
+  // (indices 2j and 2j+1 exchanged) and their first lookup goes to the table-1 half.
+  const uint32_t hsw = (uint32_t)g8 & 1u;
+  const uint32_t lb0 = hsw * 128u + (uint32_t)l8 * 16u, lb1 = (hsw ^ 1u) * 128u + (uint32_t)l8 * 16u;
+  const uint32_t swp = hsw ? 0x02030001u : 0x03020100u;
   // B: lane L builds column dword L&31 of table L>>5, i.e. rows kp + 8*(L>>5) + b.
   const int boff = (L >> 5) * KB * ldb_b + (L & 31) * 4;
 
@@ -331,9 +338,11 @@ __device__ __forceinline__ void m4rm2_tile(const MulDesc& d, int tm, int tn, cha
     if (p + 1 < nphases) build_table<WAVES>(tab, (p & 1) ^ 1, w, L, sr);
     __syncthreads();
   };
-  auto group = [&](int gd, const uint32_t (&cur)[S], uint32_t (&nxt)[S]) {
+  auto group = [&](int gd, uint32_t (&cur)[S], uint32_t (&nxt)[S]) {
     const int p0 = 2 * gd;
     if (p0 + 2 < nphases) load_a(gd + 1, nxt);
+#pragma unroll
+    for (int s = 0; s < S; ++s) cur[s] = __builtin_amdgcn_perm(cur[s], cur[s], swp);
     phase(p0, std::integral_constant<int, 0>{}, cur);
     if (p0 + 1 < nphases) phase(p0 + 1, std::integral_constant<int, 1>{}, cur);
   };
@@ -434,9 +443,10 @@ using V6 = PolicyT1<16, 32>;      // t=1, BM 512
 using V7 = PolicyT2<8, 4, 4>;     // t=2, BM 256, 8 waves
 using V8 = PolicyT1<8, 32>;       // t=1, BM 256, 8 waves
 using V9 = PolicyT1<4, 32>;       // t=1, BM 128, 4 waves
+using V10 = PolicyT2<16, 11, 2>;  // t=2, BM 1408: six tiles cover 8192 rows
 #define GF2_V(P) { P::NT, P::BM, P::TW, m4rm_group<P>, m4rm_list<P> }
 const Variant kVariants[] = {GF2_V(V0), GF2_V(V1), GF2_V(V2), GF2_V(V3), GF2_V(V4),
-                             GF2_V(V5), GF2_V(V6), GF2_V(V7), GF2_V(V8), GF2_V(V9)};
+                             GF2_V(V5), GF2_V(V6), GF2_V(V7), GF2_V(V8), GF2_V(V9), GF2_V(V10)};
 #undef GF2_V
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 

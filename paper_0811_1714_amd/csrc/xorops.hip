@@ -56,12 +56,6 @@ __device__ __forceinline__ void pre_element(const PreOp& a, int64_t i) {
   a.out[3][off] = o3;
 }
 
-__global__ void strassen_pre_kernel(PreOp a) {
-  const int64_t total = a.R * a.Wd;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x)
-    pre_element(a, i);
-}
-
 __global__ void strassen_pre_multi_kernel(const PreOp* __restrict__ ops) {
   const PreOp a = ops[blockIdx.y];
   const int64_t total = a.R * a.Wd;
@@ -93,14 +87,30 @@ __device__ __forceinline__ void post_element(const PostOp& a, int64_t i) {
   }
 }
 
-__global__ void strassen_post_kernel(PostOp a) {
+__global__ void strassen_post_multi_kernel(const PostOp* __restrict__ ops) {
+  const PostOp a = ops[blockIdx.y];
   const int64_t total = a.c[0].rows * a.c[0].wds;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x)
     post_element(a, i);
 }
 
-__global__ void strassen_post_multi_kernel(const PostOp* __restrict__ ops) {
-  const PostOp a = ops[blockIdx.y];
+// Up to kArgOps ops of one recursion depth passed by value (no device staging, so a
+// single product's passes need no host-to-device copy); blockIdx.y selects the op.
+template <class Op>
+struct OpBatch {
+  int32_t count;
+  Op op[kArgOps];
+};
+
+__global__ void strassen_pre_args_kernel(OpBatch<PreOp> b) {
+  const PreOp& a = b.op[blockIdx.y];
+  const int64_t total = a.R * a.Wd;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x)
+    pre_element(a, i);
+}
+
+__global__ void strassen_post_args_kernel(OpBatch<PostOp> b) {
+  const PostOp& a = b.op[blockIdx.y];
   const int64_t total = a.c[0].rows * a.c[0].wds;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x)
     post_element(a, i);
@@ -130,26 +140,52 @@ gf2_status fill_zero(const OView& o, hipStream_t s) {
   return hip_check(hipGetLastError(), "fill_zero launch");
 }
 
-gf2_status strassen_pre(const PreOp& op, hipStream_t s) {
-  if (op.R <= 0 || op.Wd <= 0) return GF2_OK;
-  TraceScope trace(GF2_TRACE_PRE, 1, 8.0 * 8 * op.R * op.Wd, s);   // 4 quadrants in, 4 out
-  hipLaunchKernelGGL(strassen_pre_kernel, dim3(grid_for(op.R * op.Wd)), dim3(kThreads), 0, s, op);
-  return hip_check(hipGetLastError(), "strassen_pre launch");
-}
-
-gf2_status strassen_post(const PostOp& op, hipStream_t s) {
-  const int64_t total = op.c[0].rows * op.c[0].wds;
-  if (total <= 0) return GF2_OK;
-  TraceScope trace(GF2_TRACE_POST, 1, 8.0 * 11 * total, s);   // 7 products in, 4 quadrants out
-  hipLaunchKernelGGL(strassen_post_kernel, dim3(grid_for(total)), dim3(kThreads), 0, s, op);
-  return hip_check(hipGetLastError(), "strassen_post launch");
-}
-
 // Multi-op launches: blockIdx.y selects the op; x blocks stride over its words.
 unsigned multi_x(int64_t max_elems, int n) {
   int64_t b = (max_elems + kThreads - 1) / kThreads;
   const int64_t cap = n >= 64 ? 16 : 256 * 8 / (n > 0 ? n : 1);
   return (unsigned)(b < 1 ? 1 : (b > cap ? cap : b));
+}
+
+gf2_status strassen_pre_ops(const PreOp* ops, int n, hipStream_t s) {
+  for (int base = 0; base < n; base += kArgOps) {
+    OpBatch<PreOp> b;
+    b.count = std::min(kArgOps, n - base);
+    int64_t mx = 0;
+    double bytes = 0;
+    for (int i = 0; i < b.count; ++i) {
+      b.op[i] = ops[base + i];
+      mx = std::max(mx, b.op[i].R * b.op[i].Wd);
+      bytes += 64.0 * b.op[i].R * b.op[i].Wd;
+    }
+    if (mx <= 0) continue;
+    TraceScope trace(GF2_TRACE_PRE, b.count, bytes, s);
+    hipLaunchKernelGGL(strassen_pre_args_kernel, dim3(multi_x(mx, b.count), b.count), dim3(kThreads), 0, s, b);
+    gf2_status r = hip_check(hipGetLastError(), "strassen_pre_ops launch");
+    if (r != GF2_OK) return r;
+  }
+  return GF2_OK;
+}
+
+gf2_status strassen_post_ops(const PostOp* ops, int n, hipStream_t s) {
+  for (int base = 0; base < n; base += kArgOps) {
+    OpBatch<PostOp> b;
+    b.count = std::min(kArgOps, n - base);
+    int64_t mx = 0;
+    double bytes = 0;
+    for (int i = 0; i < b.count; ++i) {
+      b.op[i] = ops[base + i];
+      const int64_t t = b.op[i].c[0].rows * b.op[i].c[0].wds;
+      mx = std::max(mx, t);
+      bytes += 88.0 * t;
+    }
+    if (mx <= 0) continue;
+    TraceScope trace(GF2_TRACE_POST, b.count, bytes, s);
+    hipLaunchKernelGGL(strassen_post_args_kernel, dim3(multi_x(mx, b.count), b.count), dim3(kThreads), 0, s, b);
+    gf2_status r = hip_check(hipGetLastError(), "strassen_post_ops launch");
+    if (r != GF2_OK) return r;
+  }
+  return GF2_OK;
 }
 
 gf2_status fill_zero_multi(const OView* dev_ops, int n, int64_t max_elems, hipStream_t s) {

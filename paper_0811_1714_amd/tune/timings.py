@@ -5,6 +5,9 @@ isolated latency (gf2_autotune), columns S..2S-1 the per-product time inside a b
 copies (gf2_autotune_batch).
 
     python -m paper_0811_1714_amd.tune.timings --count 20000 --heldout 500 --out timings.npz
+
+A run cut short by ``--budget`` is continued with ``--start <shapes done> --heldout 0``; the
+trainer concatenates the training parts of several files.
 """
 import argparse
 import os
@@ -52,11 +55,13 @@ def main():
     ap.add_argument("--seed", type=int, default=4)
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--budget", type=float, default=None, help="seconds for the training shapes")
+    ap.add_argument("--start", type=int, default=0, help="skip this many training shapes (continue a run)")
     ap.add_argument("--out", default="timings.npz")
     args = ap.parse_args()
     import paper_0811_1714_amd as g
     g.lib()
     tr_dims, tr_dens = shapes(args.seed, args.count, 11)
+    tr_dims, tr_dens = tr_dims[args.start:], tr_dens[args.start:]
     ho_dims, ho_dens = shapes(args.seed, args.heldout, 12)
     ho_ms, _ = collect(ho_dims, ho_dens, args.reps, "held-out")
     tr_ms, n = collect(tr_dims, tr_dens, args.reps, "train", args.budget)

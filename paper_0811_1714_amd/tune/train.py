@@ -89,7 +89,8 @@ class Trainer:
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--data", required=True)
+    ap.add_argument("--data", required=True, nargs="+",
+                    help="timing files; training parts are concatenated, held-out shapes come from the first")
     ap.add_argument("--out", default=DEFAULT_MODEL)
     ap.add_argument("--epochs", type=int, default=400)
     ap.add_argument("--batch", type=int, default=512)
@@ -101,9 +102,11 @@ def main():
     g.lib()
     S = g.num_candidates()
     NO = 2 * S
-    d = np.load(args.data)
-    Xtr_raw, Xho_raw = features(d["train_dims"], d["train_density"]), features(d["heldout_dims"], d["heldout_density"])
-    ms_tr, ms_ho = d["train_ms"].astype(np.float64), d["heldout_ms"].astype(np.float64)
+    parts = [np.load(f) for f in args.data]
+    d = parts[0]
+    cat = lambda key: np.concatenate([q[key] for q in parts])
+    Xtr_raw, Xho_raw = features(cat("train_dims"), cat("train_density")), features(d["heldout_dims"], d["heldout_density"])
+    ms_tr, ms_ho = cat("train_ms").astype(np.float64), d["heldout_ms"].astype(np.float64)
     mean, std = Xtr_raw.mean(axis=0), Xtr_raw.std(axis=0) + 1e-9
     Mtr = (ms_tr > 0).astype(np.float32)
     logt = np.where(ms_tr > 0, np.log(np.maximum(ms_tr, 1e-9)), 0.0)
