@@ -44,13 +44,17 @@ def parse():
     ap.add_argument("--check-rows", type=int, default=16, help="rows compared with the oracle after timing")
     ap.add_argument("--copy-calibration", action="store_true", help="run a plain 1 GiB device copy (counter scale)")
     ap.add_argument("--batch", type=int, default=0, help="also time a batch of this many log-uniform products")
+    ap.add_argument("--rect", action="store_true", help="time the rectangular and ragged products (library schedule)")
+    ap.add_argument("--odd-sweep", action="store_true",
+                    help="padding vs peeling around 2^14 and at word-misaligned sizes")
     return ap.parse_args()
 
 
 def default_schedule(g, n):
-    """Headline schedule, from the MI355X sweep: two Strassen-Winograd levels
-    (cutoff n/4) over the two-table M4RM tile of 1536 rows."""
-    return g.Schedule(g.KERNEL_M4RM, 0, n // 4 if n >= 8192 else 0, 1)
+    """Headline schedule, from the MI355X sweep (and the library's own cost model): two
+    Strassen-Winograd levels (cutoff n/4) over the two-table M4RM tile of 1408 rows, which
+    covers each 8192-row leaf of the 32768 product in six tiles."""
+    return g.Schedule(g.KERNEL_M4RM, 10, n // 4 if n >= 8192 else 0, 1)
 
 
 def m4rm_source_hash():
@@ -128,6 +132,74 @@ def sweep(g):
                 print(json.dumps({"n": n, "variant": v, "cutoff": cutoff, "ms": round(min(per), 4),
                                   "eff_bitops": 2 * n ** 3 / (min(per) * 1e-3)}), flush=True)
         del dA, dB, dC
+        torch.cuda.empty_cache()
+
+
+RECT_SHAPES = ((10000, 20000, 5000), (20001, 777, 30003), (4095, 65537, 129))
+
+
+def rect_bench(g):
+    """The rectangular and ragged products at p = 1/2 and p = 0.01 (stored dense) under the
+    library's own schedule, and the int8 matrix-core base for comparison.  Compulsory HBM
+    bytes = A + B + C once."""
+    import torch
+    import synth
+    for (m, k, n) in RECT_SHAPES:
+        for p in (0.5, 0.01):
+            A = synth.bernoulli(1, synth.TAG_A, m, k, p)
+            B = synth.bernoulli(1, synth.TAG_B, k, n, p)
+            dA, dB = to_dev(A), to_dev(B)
+            dC = torch.empty((m, (n + 63) // 64), dtype=torch.int64, device="cuda")
+            hbm = 8.0 * (m * ((k + 63) // 64) + k * ((n + 63) // 64) + m * ((n + 63) // 64))
+            for name, sched in (("library", None), ("mfma", g.Schedule(g.KERNEL_MFMA, 0, 0, 1))):
+                for _ in range(2):
+                    g.mul(dC, dA, dB, m, k, n, schedule=sched)
+                torch.cuda.synchronize()
+                evs = [torch.cuda.Event(enable_timing=True) for _ in range(11)]
+                evs[0].record()
+                for i in range(10):
+                    g.mul(dC, dA, dB, m, k, n, schedule=sched)
+                    evs[i + 1].record()
+                torch.cuda.synchronize()
+                per = [evs[i].elapsed_time(evs[i + 1]) for i in range(10)]
+                ms = float(np.median(per))
+                print(json.dumps({"m": m, "k": k, "n": n, "p": p, "schedule": name, "ms": round(ms, 4),
+                                  "eff_bitops": 2.0 * m * k * n / (ms * 1e-3),
+                                  "hbm_compulsory_bytes": hbm, "hbm_roof_ms": hbm / 8e12 * 1e3,
+                                  "word_xors": m * ((k + 7) // 8) * ((n + 63) // 64),
+                                  "valu_roof_ms": m * ((k + 7) // 8) * ((n + 63) // 64) / VALU_WORD_XOR_PEAK * 1e3}),
+                      flush=True)
+            del dA, dB, dC
+            torch.cuda.empty_cache()
+
+
+ODD_SIZES = (16383, 16384, 16385, 16320, 16448, 16000)
+
+
+def odd_sweep(g):
+    """Odd sizes in Strassen-Winograd: virtual zero padding against peeling, n x n products
+    around 2^14 and at sizes that are not multiples of 128.  Two levels for every size (the
+    cutoff n/4 + 128 stops both rules after two halvings), 1408-row tiles."""
+    import torch
+    import synth
+    for n in ODD_SIZES:
+        A = synth.uniform(1, synth.TAG_A, n, n)
+        B = synth.uniform(1, synth.TAG_B, n, n)
+        dA, dB = to_dev(A), to_dev(B)
+        dC = torch.empty_like(dA)
+        outs = {}
+        for odd, name in ((g.ODD_PAD, "pad"), (g.ODD_PEEL, "peel")):
+            s = g.Schedule(g.KERNEL_M4RM, 10, n // 4 + 128, 1, odd)
+            ws = g.workspace_bytes(n, n, n, s)
+            if ws:
+                g.reserve_workspace(ws)
+            ms, per = time_product(g, dA, dB, dC, n, s, 5, 2)
+            outs[name] = dC.clone()
+            print(json.dumps({"n": n, "odd": name, "cutoff": s.cutoff, "ms": round(float(np.median(per)), 4),
+                              "eff_bitops": 2 * n ** 3 / (float(np.median(per)) * 1e-3),
+                              "workspace_bytes": ws}), flush=True)
+        assert torch.equal(outs["pad"], outs["peel"]), f"n={n}: peeling and padding differ"
+        del dA, dB, dC, outs
         torch.cuda.empty_cache()
 
 
@@ -220,6 +292,12 @@ def main():
     g.lib()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.odd_sweep:
+        odd_sweep(g)
+        return
+    if args.rect:
+        rect_bench(g)
         return
     if args.sweep:
         global SWEEP_N, SWEEP_VARIANTS

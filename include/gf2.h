@@ -66,13 +66,22 @@ enum {
   GF2_KERNEL_CUBIC = 3  /* AND + popcount parity against B transposed (Section 2.3) */
 };
 
+/* Odd sizes inside Strassen-Winograd (Section 4).  PAD: every split is at a word
+ * border and the missing rows/columns of the smaller halves are treated as zero
+ * (nothing is copied).  PEEL: each recursion node recurses on its largest part with
+ * an even row count and k, n multiples of 128, and adds the peeled rows, columns and
+ * inner slice with non-recursive base-case products. */
+enum { GF2_ODD_PAD = 0, GF2_ODD_PEEL = 1 };
+
 /* A schedule: which base kernel, its tile variant, the Strassen-Winograd
- * crossover and the number of k slices.  Zero fields mean "default". */
+ * crossover, the number of k slices and the odd-size rule.  Zero fields mean
+ * "default". */
 typedef struct gf2_schedule {
   int32_t kernel;   /* GF2_KERNEL_* */
   int32_t variant;  /* kernel tile variant (see gf2_kernel_variants) */
   int32_t cutoff;   /* recurse while min(m, k, n) > cutoff; 0 = no recursion (Section 5, c_o) */
   int32_t splitk;   /* k split into this many slices XOR-combined into C; 0 or 1 = none */
+  int32_t odd;      /* GF2_ODD_PAD or GF2_ODD_PEEL (only with cutoff > 0) */
 } gf2_schedule;
 
 /* C := A*B.  Section 1 / Section 2.3 definition above.  m, k, n >= 0.

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libgf2.so")
 _LIB = None
 
 KERNEL_AUTO, KERNEL_M4RM, KERNEL_MFMA, KERNEL_CUBIC = 0, 1, 2, 3
+ODD_PAD, ODD_PEEL = 0, 1
 
 STATUS = {0: "GF2_OK", 1: "GF2_ERR_INVALID_ARG", 2: "GF2_ERR_ALIAS", 3: "GF2_ERR_ALLOC", 4: "GF2_ERR_CAPTURE",
           5: "GF2_ERR_DEVICE", 6: "GF2_ERR_UNSUPPORTED"}
@@ -31,10 +32,11 @@ class GF2Error(RuntimeError):
 
 class Schedule(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_int32), ("variant", ctypes.c_int32), ("cutoff", ctypes.c_int32),
-                ("splitk", ctypes.c_int32)]
+                ("splitk", ctypes.c_int32), ("odd", ctypes.c_int32)]
 
     def __repr__(self):
-        return f"Schedule(kernel={self.kernel}, variant={self.variant}, cutoff={self.cutoff}, splitk={self.splitk})"
+        return (f"Schedule(kernel={self.kernel}, variant={self.variant}, cutoff={self.cutoff}, "
+                f"splitk={self.splitk}, odd={self.odd})")
 
 
 def lib():

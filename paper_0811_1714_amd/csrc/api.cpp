@@ -236,6 +236,7 @@ gf2_schedule resolve(const gf2_schedule* req, int64_t m, int64_t k, int64_t n, h
     if (req->kernel != GF2_KERNEL_AUTO || req->variant) s.variant = req->variant;
     s.cutoff = req->cutoff;
     if (req->splitk > 0) s.splitk = req->splitk;
+    s.odd = req->odd;
   }
   return s;
 }
@@ -284,6 +285,7 @@ gf2_status validate_sched(const gf2_schedule* s) {
     return set_error(GF2_ERR_INVALID_ARG, "variant %d out of range", s->variant);
   if (s->cutoff < 0) return set_error(GF2_ERR_INVALID_ARG, "negative cutoff");
   if (s->splitk < 0 || s->splitk > kMaxGroup) return set_error(GF2_ERR_INVALID_ARG, "splitk must be in [0, %d]", kMaxGroup);
+  if (s->odd != GF2_ODD_PAD && s->odd != GF2_ODD_PEEL) return set_error(GF2_ERR_INVALID_ARG, "unknown odd-size rule %d", s->odd);
   return GF2_OK;
 }
 
@@ -335,6 +337,11 @@ struct StrassenPlan {
   std::vector<PreOp> pre;
   std::vector<MulDesc> leaves;
   std::vector<PostOp> post;
+  // Peeling fix-ups.  Inner-slice ones (C ^= A[:, k':] B[k':, :]) run after the
+  // post-additions of their node's depth, which write the C they add to; peeled rows and
+  // columns only need their node's operands and run after the leaves.
+  std::vector<std::pair<int, MulDesc>> kfix;
+  std::vector<MulDesc> fix;
   size_t ws_words = 0;
 };
 
@@ -350,11 +357,34 @@ bool splittable(int64_t m, int64_t k, int64_t n, int64_t cutoff) {
 // post-ops children first; the leaves run all at once in between.  ``base`` == nullptr
 // only sizes the workspace.
 void plan_node(StrassenPlan& pl, uint64_t* base, const View& A, const View& B, uint64_t* C, int64_t ldc,
-               int out_mode, int64_t cutoff, int depth = 0) {
+               int out_mode, int64_t cutoff, int odd, int depth = 0) {
   const int64_t m = A.rows, k = A.cols, n = B.cols;
   if (!splittable(m, k, n, cutoff)) {
     pl.leaves.push_back(make_desc(A, B, C, ldc, out_mode));
     return;
+  }
+  if (odd == GF2_ODD_PEEL) {
+    // Section 4, peeling: recurse on the largest part that halves exactly on word
+    // borders (rows even, k and n multiples of 128) and add the rest without recursion:
+    //   C[:m',:n'] = A[:m',:k'] B[:k',:n'] + A[:m',k':] B[k':,:n']
+    //   C[:m',n':] = A[:m',:] B[:,n':]        C[m':,:] = A[m':,:] B
+    const int64_t me = m & ~int64_t(1), ke = k & ~int64_t(127), ne = n & ~int64_t(127);
+    if (me != m || ke != k || ne != n) {
+      if (!splittable(me, ke, ne, cutoff)) {
+        pl.leaves.push_back(make_desc(A, B, C, ldc, out_mode));
+        return;
+      }
+      plan_node(pl, base, View{A.p, A.ld, me, ke}, View{B.p, B.ld, ke, ne}, C, ldc, out_mode, cutoff, odd, depth);
+      if (ke < k)
+        pl.kfix.push_back({depth, make_desc(View{A.p + ke / 64, A.ld, me, k - ke}, View{B.p + ke * B.ld, B.ld, k - ke, ne},
+                                            C, ldc, OUT_XOR)});
+      if (ne < n)
+        pl.fix.push_back(make_desc(View{A.p, A.ld, me, k}, View{B.p + ne / 64, B.ld, k, n - ne}, C + ne / 64, ldc,
+                                   out_mode));
+      if (me < m)
+        pl.fix.push_back(make_desc(View{A.p + me * A.ld, A.ld, m - me, k}, B, C + me * ldc, ldc, out_mode));
+      return;
+    }
   }
   const int64_t m0 = (m + 1) / 2, m1 = m - m0;
   const int64_t k0w = (words(k) + 1) / 2, k0 = 64 * k0w, k1 = k - k0;
@@ -396,13 +426,13 @@ void plan_node(StrassenPlan& pl, uint64_t* base, const View& A, const View& B, u
   const View B_NW{B.p, B.ld, k0, n0}, B_SW{B.p + k0 * B.ld, B.ld, k1, n0}, B_SE{B.p + k0 * B.ld + n0w, B.ld, k1, n1};
   const View S0{S[0], k0w, m0, k0}, S1{S[1], k0w, m0, k0}, S2{S[2], k0w, m0, k0}, S3{S[3], k0w, m0, k1};
   const View T0{T[0], n0w, k0, n0}, T1{T[1], n0w, k0, n0}, T2{T[2], n0w, k0, n0}, T3{T[3], n0w, k1, n0};
-  plan_node(pl, base, A_NW, B_NW, P[0], n0w, OUT_STORE, cutoff, depth + 1);   // P0 = A_NW B_NW
-  plan_node(pl, base, A_NE, B_SW, P[1], n0w, OUT_STORE, cutoff, depth + 1);   // P1 = A_NE B_SW
-  plan_node(pl, base, S3, B_SE, P[2], n0w, OUT_STORE, cutoff, depth + 1);     // P2 = S3 B_SE
-  plan_node(pl, base, A_SE, T3, P[3], n0w, OUT_STORE, cutoff, depth + 1);     // P3 = A_SE T3
-  plan_node(pl, base, S0, T0, P[4], n0w, OUT_STORE, cutoff, depth + 1);       // P4 = S0 T0
-  plan_node(pl, base, S1, T1, P[5], n0w, OUT_STORE, cutoff, depth + 1);       // P5 = S1 T1
-  plan_node(pl, base, S2, T2, P[6], n0w, OUT_STORE, cutoff, depth + 1);       // P6 = S2 T2
+  plan_node(pl, base, A_NW, B_NW, P[0], n0w, OUT_STORE, cutoff, odd, depth + 1);   // P0 = A_NW B_NW
+  plan_node(pl, base, A_NE, B_SW, P[1], n0w, OUT_STORE, cutoff, odd, depth + 1);   // P1 = A_NE B_SW
+  plan_node(pl, base, S3, B_SE, P[2], n0w, OUT_STORE, cutoff, odd, depth + 1);     // P2 = S3 B_SE
+  plan_node(pl, base, A_SE, T3, P[3], n0w, OUT_STORE, cutoff, odd, depth + 1);     // P3 = A_SE T3
+  plan_node(pl, base, S0, T0, P[4], n0w, OUT_STORE, cutoff, odd, depth + 1);       // P4 = S0 T0
+  plan_node(pl, base, S1, T1, P[5], n0w, OUT_STORE, cutoff, odd, depth + 1);       // P5 = S1 T1
+  plan_node(pl, base, S2, T2, P[6], n0w, OUT_STORE, cutoff, odd, depth + 1);       // P6 = S2 T2
 
   PostOp po;
   for (int i = 0; i < 7; ++i) po.P[i] = P[i];
@@ -429,6 +459,34 @@ void plan_splitk(std::vector<MulDesc>& out, const View& A, const View& B, uint64
   }
 }
 
+// Peeling fix-ups are thin products (a few rows, columns or k) with long other sides.  On
+// the M4RM kernel each gets a tile height that suits its rows and its k cut into slices
+// of about 2048 XOR-ed into C, so no tile runs much longer than a leaf tile; a stored
+// result has its region zeroed first.
+gf2_status run_fixups(const gf2_schedule& s, const std::vector<MulDesc>& ds, uint64_t* scratch, hipStream_t st) {
+  if (ds.empty()) return GF2_OK;
+  if (s.kernel != GF2_KERNEL_M4RM) return run_base(s, ds, scratch, st);
+  gf2_status r;
+  std::map<int, std::vector<MulDesc>> by_variant;
+  for (const MulDesc& d : ds) {
+    if (d.m <= 0 || d.n <= 0 || d.k <= 0) continue;
+    const int v = d.m <= 128 ? 4 : d.m <= 256 ? 3 : d.m <= 512 ? 2 : s.variant;
+    const int sk = (int)std::min<int64_t>(kMaxGroup, std::max<int64_t>(1, (d.k + 2047) / 2048));
+    if (sk > 1 && d.out == OUT_STORE)
+      if ((r = fill_zero(OView{d.C, d.ldc, d.m, words(d.n), tail_of(d.n)}, st)) != GF2_OK) return r;
+    if (sk > 1) {
+      std::vector<MulDesc> parts;
+      plan_splitk(parts, View{d.A, d.lda, d.m, d.k}, View{d.B, d.ldb, d.k, d.n}, d.C, d.ldc, sk);
+      by_variant[v].insert(by_variant[v].end(), parts.begin(), parts.end());
+    } else {
+      by_variant[v].push_back(d);
+    }
+  }
+  for (const auto& kv : by_variant)
+    if ((r = m4rm_launch_group(kv.second.data(), (int)kv.second.size(), kv.first, st)) != GF2_OK) return r;
+  return GF2_OK;
+}
+
 // Leaves of the product and the workspace they need: Strassen temporaries first, then
 // the base kernel's scratch.  ``base`` == nullptr sizes only.
 struct ProductPlan {
@@ -444,8 +502,11 @@ void plan_product(ProductPlan& pp, uint64_t* base, uint64_t* C, int64_t ldc, con
   const int out = accumulate ? OUT_XOR : OUT_STORE;
   const View Av{A, lda, m, k}, Bv{B, ldb, k, n};
   if (splittable(m, k, n, s.cutoff)) {
-    plan_node(pp.st, base, Av, Bv, C, ldc, out, s.cutoff);
-    pp.scratch_words = base_scratch_words(s, pp.st.leaves);
+    plan_node(pp.st, base, Av, Bv, C, ldc, out, s.cutoff, s.odd);
+    std::vector<MulDesc> all = pp.st.leaves;
+    for (const auto& f : pp.st.kfix) all.push_back(f.second);
+    all.insert(all.end(), pp.st.fix.begin(), pp.st.fix.end());
+    pp.scratch_words = base_scratch_words(s, all);
   } else {
     if (s.splitk > 1 && words(k) > 1) plan_splitk(pp.leaves, Av, Bv, C, ldc, s.splitk);
     else pp.leaves.push_back(make_desc(Av, Bv, C, ldc, out));
@@ -478,7 +539,6 @@ gf2_status execute(uint64_t* C, int64_t ldc, const uint64_t* A, int64_t lda, con
     std::vector<PreOp> pre = pp.st.pre;
     std::vector<PostOp> post = pp.st.post;
     std::stable_sort(pre.begin(), pre.end(), [](const PreOp& a, const PreOp& b) { return a.depth < b.depth; });
-    std::stable_sort(post.begin(), post.end(), [](const PostOp& a, const PostOp& b) { return a.depth > b.depth; });
     for (size_t i = 0; i < pre.size();) {
       size_t j = i;
       while (j < pre.size() && pre[j].depth == pre[i].depth) ++j;
@@ -486,11 +546,19 @@ gf2_status execute(uint64_t* C, int64_t ldc, const uint64_t* A, int64_t lda, con
       i = j;
     }
     if ((r = run_base(s, pp.st.leaves, scratch, st)) != GF2_OK) return r;
-    for (size_t i = 0; i < post.size();) {
-      size_t j = i;
-      while (j < post.size() && post[j].depth == post[i].depth) ++j;
-      if ((r = strassen_post_ops(post.data() + i, (int)(j - i), st)) != GF2_OK) return r;
-      i = j;
+    if ((r = run_fixups(s, pp.st.fix, scratch, st)) != GF2_OK) return r;
+    int maxd = 0;
+    for (const auto& f : pp.st.kfix) maxd = std::max(maxd, f.first);
+    for (const PostOp& p : post) maxd = std::max(maxd, p.depth);
+    for (int d = maxd; d >= 0; --d) {
+      std::vector<PostOp> pd;
+      for (const PostOp& p : post)
+        if (p.depth == d) pd.push_back(p);
+      if ((r = strassen_post_ops(pd.data(), (int)pd.size(), st)) != GF2_OK) return r;
+      std::vector<MulDesc> fd;
+      for (const auto& f : pp.st.kfix)
+        if (f.first == d) fd.push_back(f.second);
+      if ((r = run_fixups(s, fd, scratch, st)) != GF2_OK) return r;
     }
     return GF2_OK;
   }
@@ -844,6 +912,8 @@ gf2_status build_batch_plan(const gf2_problem* probs, int64_t count, BatchPlanIm
     ProductPlan pp;
     plan_product(pp, P.ws ? P.ws + ws_off[i] : nullptr, p.C, p.ldc, p.A, p.lda, p.B, p.ldb, p.m, p.k, p.n,
                  p.accumulate != 0, s);
+    if (!pp.st.kfix.empty() || !pp.st.fix.empty())
+      return set_error(GF2_ERR_UNSUPPORTED, "peeling is not supported in batches");
     if (!pp.st.leaves.empty()) {
       P.pre.insert(P.pre.end(), pp.st.pre.begin(), pp.st.pre.end());
       P.post.insert(P.post.end(), pp.st.post.begin(), pp.st.post.end());

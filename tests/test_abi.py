@@ -70,7 +70,7 @@ def test_validation_codes(fn):
 def test_schedule_validation():
     L = g.lib()
     bad = [g.Schedule(9, 0, 0, 1), g.Schedule(g.KERNEL_M4RM, 99, 0, 1), g.Schedule(g.KERNEL_M4RM, 0, -1, 1),
-           g.Schedule(g.KERNEL_M4RM, 0, 0, 1000)]
+           g.Schedule(g.KERNEL_M4RM, 0, 0, 1000), g.Schedule(g.KERNEL_M4RM, 0, 512, 1, 2)]
     for s in bad:
         r = L.gf2_mul_sched(P(0x10000), 2, P(0x20000), 2, P(0x30000), 2, 5, 5, 5, 0, ctypes.byref(s), None)
         assert r in (1, 6), (s, r)
@@ -106,3 +106,24 @@ def test_batch_validation_without_device():
     assert run([prob(0x10000, 0x20000, 0x30000), prob(0x60000, 0x10000, 0x50000)]) == 2        # C is another's A
     assert L.gf2_mul_batched(None, 3, None) == 1
     assert L.gf2_num_candidates() >= 8
+
+
+def test_schedule_struct_layout():
+    """gf2_schedule is five int32 fields (kernel, variant, cutoff, splitk, odd)."""
+    import ctypes
+    import paper_0811_1714_amd as g
+    assert ctypes.sizeof(g.Schedule) == 20
+    assert [f[0] for f in g.Schedule._fields_] == ["kernel", "variant", "cutoff", "splitk", "odd"]
+    assert (g.ODD_PAD, g.ODD_PEEL) == (0, 1)
+
+
+def test_peeling_workspace_is_sized_for_the_aligned_core():
+    """Peeling recurses on the largest part with even rows and k, n multiples of 128, so a
+    2^10+1 product needs the temporaries of the 1024 core's node (quadrants of 512 x 8 words)."""
+    import paper_0811_1714_amd as g
+    peel = g.workspace_bytes(1025, 1025, 1025, g.Schedule(g.KERNEL_M4RM, 0, 512, 1, g.ODD_PEEL))
+    core = g.workspace_bytes(1024, 1024, 1024, g.Schedule(g.KERNEL_M4RM, 0, 512, 1, g.ODD_PAD))
+    pad = g.workspace_bytes(1025, 1025, 1025, g.Schedule(g.KERNEL_M4RM, 0, 512, 1, g.ODD_PAD))
+    assert peel == core == 15 * 512 * 8 * 8
+    assert pad > peel     # padding splits at 513 rows / 9 words
+

@@ -20,9 +20,9 @@ def g():
     return g
 
 
-def M4RM(variant=0, cutoff=0, splitk=1):
+def M4RM(variant=0, cutoff=0, splitk=1, odd=0):
     import paper_0811_1714_amd as g
-    return g.Schedule(g.KERNEL_M4RM, variant, cutoff, splitk)
+    return g.Schedule(g.KERNEL_M4RM, variant, cutoff, splitk, odd)
 
 
 def test_config_1024_square_plain_m4rm(g):
@@ -65,6 +65,20 @@ def test_strassen_winograd_any_cutoff_same_bits(g, m, k, n, cutoff):
     got = run_and_check(g, m, k, n, schedule=M4RM(0, cutoff), seed=7)
     assert np.array_equal(base, got)
     run_and_check(g, m, k, n, schedule=M4RM(3, cutoff), seed=8, accumulate=True, ldc_pad=1)
+
+
+@pytest.mark.parametrize("m,k,n,cutoff", [(257, 257, 257, 64), (1025, 1023, 1021, 256), (300, 777, 129, 64),
+                                          (2049, 2050, 2051, 512), (1001, 3000, 700, 128), (130, 4097, 1000, 64)])
+def test_peeling_same_bits_as_padding(g, m, k, n, cutoff):
+    # Section 4: peeling and (virtual) padding reach the same product.
+    print(f"peel {(m, k, n)} cutoff {cutoff}", flush=True)
+    pad = run_and_check(g, m, k, n, schedule=M4RM(1, cutoff), seed=12)
+    peel = run_and_check(g, m, k, n, schedule=M4RM(1, cutoff, odd=1), seed=12)
+    assert np.array_equal(pad, peel)
+    run_and_check(g, m, k, n, schedule=M4RM(3, cutoff, odd=1), seed=13, accumulate=True, ldc_pad=1, lda_pad=1)
+    import paper_0811_1714_amd as gg
+    run_and_check(g, m, k, n, schedule=gg.Schedule(gg.KERNEL_MFMA, 0, cutoff, 1, 1), seed=14, ldb_pad=2)
+    run_and_check(g, m, k, n, schedule=gg.Schedule(gg.KERNEL_CUBIC, 0, cutoff, 1, 1), seed=15)
 
 
 def test_degenerate_shapes(g):
