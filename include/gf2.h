@@ -19,8 +19,10 @@
  *   - Bits at columns >= cols in a row's last word are padding.  Inputs'
  *     padding is ignored.  gf2_mul writes C's padding as 0; gf2_addmul leaves
  *     it unchanged.
- *   - Words ceil(cols/64) .. ld-1 of a row (the stride gap) are never read
- *     or written.
+ *   - Words ceil(cols/64) .. ld-1 of a row (the stride gap) are never
+ *     written and never affect the result.  Kernels may read the gap of an A
+ *     or B row that has a later row (the bytes lie inside the matrix); they
+ *     never read past the last row's last valid word.
  *   - Dimensions are in entries (bits); ld is in words.
  *
  * MEMORY AND OWNERSHIP.  A, B and C are device pointers (8-byte aligned) owned
@@ -197,6 +199,12 @@ gf2_status gf2_set_model(const float* params, int64_t count, const float* norm);
 /* Candidate the current policy picks for a product of this shape (batch != 0: only
  * schedules the persistent kernel can run). */
 int32_t gf2_choose_schedule(int64_t m, int64_t k, int64_t n, int32_t batch);
+/* The schedule gf2_mul_sched(..., req, ...) runs for a product of this shape under the
+ * current policy; req NULL is the library's own choice (for large products the M4RM
+ * tile height, Strassen-Winograd cutoff and k split of lowest predicted time, Section 5).
+ * Under GF2_POLICY_AUTOTUNE this may time the candidates first.  *out is written on
+ * GF2_OK; negative dimensions, a NULL out or an invalid req give GF2_ERR_INVALID_ARG. */
+gf2_status gf2_resolve_schedule(int64_t m, int64_t k, int64_t n, const gf2_schedule* req, gf2_schedule* out);
 
 /* Number of tile variants of a base kernel (0 for an unknown kernel). */
 int32_t gf2_kernel_variants(int32_t kernel);

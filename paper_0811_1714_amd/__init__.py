@@ -55,6 +55,8 @@ def lib():
     L.gf2_mul_sched.argtypes = mm + [I32, ctypes.POINTER(Schedule), P]
     for f in (L.gf2_mul, L.gf2_addmul, L.gf2_mul_sched):
         f.restype = ctypes.c_int
+    L.gf2_resolve_schedule.argtypes = [I64, I64, I64, ctypes.POINTER(Schedule), ctypes.POINTER(Schedule)]
+    L.gf2_resolve_schedule.restype = ctypes.c_int
     L.gf2_kernel_variants.argtypes = [I32]
     L.gf2_kernel_variants.restype = I32
     L.gf2_workspace_bytes.argtypes = [I64, I64, I64, ctypes.POINTER(Schedule)]
@@ -272,6 +274,14 @@ def get_policy() -> int:
 
 def choose_schedule(m, k, n, batch=False) -> int:
     return int(lib().gf2_choose_schedule(m, k, n, int(batch)))
+
+
+def resolve_schedule(m, k, n, schedule: Schedule | None = None) -> Schedule:
+    """The schedule gf2_mul_sched runs for this shape (``schedule`` None: the library's choice)."""
+    out = Schedule()
+    _check(lib().gf2_resolve_schedule(m, k, n, ctypes.byref(schedule) if schedule is not None else None,
+                                      ctypes.byref(out)))
+    return out
 
 
 def autotune(m, k, n, density=0.5, reps=3):

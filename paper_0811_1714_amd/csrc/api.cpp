@@ -145,25 +145,37 @@ int compute_units() {
   return c;
 }
 
-// Predicted time (ms) of an M4RM schedule on MI355X.  A tile of the 16-wave two-table
-// kernel costs, per 16-row phase of B, a fixed part (table build, barrier, B loads), a
-// part per tile row (lookups) and a cache-miss part that grows with the leaf's B beyond
-// 8 MiB; tiles of one launch run in rounds of one per compute unit.  Strassen-Winograd
-// passes move about (2mk + 2kn + 2.75mn)/8 bytes per node.  The constants were fitted to
-// square products of 8192, 16384 and 32768 at every tile height and depth.
+// Predicted time (ms) of an M4RM schedule on MI355X, fitted to 150 timed products
+// (squares of 8192-32768 at every tile, depth and k split, and the rectangular shapes):
+//   * tiles run in rounds of one per compute unit; a Strassen leaf launch whose last round
+//     is at most half full spreads that round's work over all units (``run_leaves``);
+//   * a tile costs, per barrier phase of B rows, 0.60 us (table build, barrier, B loads)
+//     plus 0.65 ns per tile row (lookups);
+//   * operand traffic (A once per column tile, B once per row tile) at 4 TB/s, Strassen
+//     passes ((2mk + 2kn + 2.75mn)/8 bytes per node) at 3 TB/s, and a k split's zeroing
+//     at 3 TB/s plus its atomic XORs at 1 TB/s.
 struct CostAcc {
-  double tile_ms = 0, add_bytes = 0;
-  int64_t tiles = 0;
+  double tile_ms = 0, add_bytes = 0, operand_bytes = 0;
+  int64_t tiles = 0, leaves = 0;
 };
-constexpr double kPhaseMs = 5.75e-4, kRowPhaseMs = 6.5e-7, kMissMs = 1.25e-4, kAddBytesPerMs = 2.0e9;
+constexpr double kPhaseMs = 6.0e-4, kRowPhaseMs = 6.5e-7, kAddBytesPerMs = 3.0e9, kAtomicBytesPerMs = 1.0e9,
+                 kOperandBytesPerMs = 4.0e9;
 
-void cost_walk(int64_t m, int64_t k, int64_t n, int64_t cutoff, int v, CostAcc& a) {
+// ``sk`` > 1 (no recursion): k in sk slices, each a tile of its own, XOR-ed atomically into
+// a zeroed C.
+void cost_walk(int64_t m, int64_t k, int64_t n, int64_t cutoff, int v, CostAcc& a, int sk = 1) {
   if (!splittable(m, k, n, cutoff)) {
-    const int64_t t = tiles_for(m, n, v);
-    const double bbytes = (double)k * (double)n / 8.0;
-    const double miss = bbytes > 8.0 * (1 << 20) ? kMissMs * std::log2(bbytes / (8.0 * (1 << 20))) : 0.0;
+    const int64_t bm = m4rm_tile_rows(v), tw = m4rm_tile_words(v), pr = m4rm_phase_rows(v);
+    const int64_t rt = (m + bm - 1) / bm, ct = (words(n) + tw - 1) / tw, t = rt * ct * sk;
+    const int64_t ks = sk > 1 ? std::min<int64_t>(k, 64 * ((words(k) + sk - 1) / sk)) : k;
     a.tiles += t;
-    a.tile_ms += (double)t * (double)((k + 15) / 16) * (kPhaseMs + kRowPhaseMs * m4rm_tile_rows(v) + miss);
+    a.leaves += 1;
+    a.tile_ms += (double)t * (double)((ks + pr - 1) / pr) * (kPhaseMs + kRowPhaseMs * (double)bm);
+    a.operand_bytes += 8.0 * ((double)m * words(k) * ct + (double)k * words(n) * rt);
+    if (sk > 1) {
+      const double cbytes = 8.0 * (double)m * (double)words(n);
+      a.add_bytes += cbytes + cbytes * sk * (kAddBytesPerMs / kAtomicBytesPerMs);
+    }
     return;
   }
   a.add_bytes += (2.0 * m * k + 2.0 * k * n + 2.75 * m * n) / 8.0;
@@ -179,32 +191,43 @@ void cost_walk(int64_t m, int64_t k, int64_t n, int64_t cutoff, int v, CostAcc& 
   cost_walk(m1, k1, n0, cutoff, v, a);   // P3
 }
 
-double predicted_ms(int64_t m, int64_t k, int64_t n, int64_t cutoff, int v) {
+double predicted_ms(int64_t m, int64_t k, int64_t n, int64_t cutoff, int v, int sk = 1) {
   CostAcc a;
-  cost_walk(m, k, n, cutoff, v, a);
+  cost_walk(m, k, n, cutoff, v, a, sk);
   if (a.tiles == 0) return 0;
   const int64_t cus = compute_units();
-  const double rounds = (double)((a.tiles + cus - 1) / cus);
-  return rounds * a.tile_ms / (double)a.tiles + a.add_bytes / kAddBytesPerMs;
+  const int64_t full = (a.tiles + cus - 1) / cus, tail = a.tiles - (full - 1) * cus;
+  const bool spread = full >= 2 && 2 * tail <= cus && a.leaves >= 2 && a.leaves <= kMaxGroup;
+  const double rounds = spread ? (double)(full - 1) + (double)tail / (double)cus : (double)full;
+  return rounds * a.tile_ms / (double)a.tiles + a.add_bytes / kAddBytesPerMs + a.operand_bytes / kOperandBytesPerMs;
 }
 
 // Default schedule for a shape (the fixed heuristic, used when nothing better is known).
-// Large products (smallest dimension >= 4096): the M4RM tile height and Strassen-Winograd
-// depth with the lowest predicted time.  Smaller ones: the tallest tile that still gives
-// every compute unit work, and k split when there are too few C tiles to fill them.
+// Products of >= 2^30 bit-operations: the M4RM tile height, Strassen-Winograd depth and
+// k split with the lowest predicted time.  Smaller ones: the tallest tile that still
+// gives every compute unit work, and k split when there are too few C tiles to fill them.
 gf2_schedule default_schedule(int64_t m, int64_t k, int64_t n) {
   gf2_schedule s{};
   s.kernel = GF2_KERNEL_M4RM;
   s.splitk = 1;
   const int64_t mn = m < n ? (m < k ? m : k) : (n < k ? n : k);
-  if (mn >= 4096) {
+  if ((double)m * (double)k * (double)n >= 1073741824.0) {
     double best = -1;
     for (int64_t cutoff : {int64_t(0), mn / 2, mn / 4, mn / 8}) {
       if (cutoff && cutoff < 2048) continue;
-      for (int v : {0, 10, 1, 2, 3}) {
+      const bool recurse = cutoff > 0 && splittable(m, k, n, cutoff);
+      for (int v : {0, 10, 1, 2, 3, 4, 11, 12, 13}) {
         if (v >= m4rm_num_variants()) continue;
-        const double t = predicted_ms(m, k, n, cutoff, v);
-        if (best < 0 || t < best) { best = t; s.variant = v; s.cutoff = (int32_t)cutoff; }
+        for (int sk : {1, 2, 4, 8, 16, 32}) {
+          if (sk > 1 && (recurse || words(k) / sk < 16)) continue;
+          const double t = predicted_ms(m, k, n, cutoff, v, sk);
+          if (best < 0 || t < best) {
+            best = t;
+            s.variant = v;
+            s.cutoff = (int32_t)cutoff;
+            s.splitk = sk;
+          }
+        }
       }
     }
     return s;
@@ -487,6 +510,44 @@ gf2_status run_fixups(const gf2_schedule& s, const std::vector<MulDesc>& ds, uin
   return GF2_OK;
 }
 
+// Strassen leaves in one launch.  Equal tiles run in rounds of one per compute unit; when
+// the last round would be less than half full, the leaves whose tiles make up that round
+// are cut into k slices (XOR-ed atomically into their zeroed results) that are dispatched
+// last, so the short slices spread over the whole machine instead of a few units running
+// one more full round.  Example: 32768^3 at two levels, 1408-row tiles: 2352 tiles are
+// 9.19 rounds on 256 units; one leaf of 48 tiles becomes 5 x 48 slices of a fifth each.
+gf2_status run_leaves(const gf2_schedule& s, const std::vector<MulDesc>& leaves, uint64_t* scratch, hipStream_t st) {
+  if (s.kernel != GF2_KERNEL_M4RM || leaves.size() < 2 || leaves.size() > (size_t)kMaxGroup)
+    return run_base(s, leaves, scratch, st);
+  const int64_t cus = compute_units();
+  std::vector<int64_t> t(leaves.size());
+  int64_t T = 0;
+  for (size_t i = 0; i < leaves.size(); ++i) T += (t[i] = m4rm_tiles(leaves[i], s.variant));
+  const int64_t rounds = (T + cus - 1) / cus, tail = T - (rounds - 1) * cus;
+  if (rounds < 2 || 2 * tail > cus) return run_base(s, leaves, scratch, st);
+  size_t first = leaves.size();
+  int64_t cover = 0;
+  while (first > 0 && cover < tail) cover += t[--first];
+  const int64_t sk = std::max<int64_t>(2, std::min<int64_t>(8, (cus + cover / 2) / cover));
+  std::vector<MulDesc> main(leaves.begin(), leaves.begin() + (std::ptrdiff_t)first), slices, zero;
+  for (size_t i = first; i < leaves.size(); ++i) {
+    const MulDesc& d = leaves[i];
+    const int64_t ski = std::min<int64_t>(sk, words(d.k) / 16);
+    if (ski < 2) {
+      main.push_back(d);
+      continue;
+    }
+    if (d.out == OUT_STORE) zero.push_back(d);
+    plan_splitk(slices, View{d.A, d.lda, d.m, d.k}, View{d.B, d.ldb, d.k, d.n}, d.C, d.ldc, (int)ski);
+  }
+  if (slices.empty() || main.size() + slices.size() > (size_t)kMaxGroup) return run_base(s, leaves, scratch, st);
+  gf2_status r;
+  for (const MulDesc& d : zero)
+    if ((r = fill_zero(OView{d.C, d.ldc, d.m, words(d.n), tail_of(d.n)}, st)) != GF2_OK) return r;
+  main.insert(main.end(), slices.begin(), slices.end());
+  return m4rm_launch_group(main.data(), (int)main.size(), s.variant, st, (int)slices.size());
+}
+
 // Leaves of the product and the workspace they need: Strassen temporaries first, then
 // the base kernel's scratch.  ``base`` == nullptr sizes only.
 struct ProductPlan {
@@ -545,7 +606,7 @@ gf2_status execute(uint64_t* C, int64_t ldc, const uint64_t* A, int64_t lda, con
       if ((r = strassen_pre_ops(pre.data() + i, (int)(j - i), st)) != GF2_OK) return r;
       i = j;
     }
-    if ((r = run_base(s, pp.st.leaves, scratch, st)) != GF2_OK) return r;
+    if ((r = run_leaves(s, pp.st.leaves, scratch, st)) != GF2_OK) return r;
     if ((r = run_fixups(s, pp.st.fix, scratch, st)) != GF2_OK) return r;
     int maxd = 0;
     for (const auto& f : pp.st.kfix) maxd = std::max(maxd, f.first);
@@ -1163,6 +1224,16 @@ gf2_status gf2_set_policy(int32_t policy) {
 }
 
 int32_t gf2_get_policy(void) { return g_policy.load(); }
+
+gf2_status gf2_resolve_schedule(int64_t m, int64_t k, int64_t n, const gf2_schedule* req, gf2_schedule* out) {
+  g_err[0] = 0;
+  if (m < 0 || k < 0 || n < 0) return set_error(GF2_ERR_INVALID_ARG, "negative dimension");
+  if (!out) return set_error(GF2_ERR_INVALID_ARG, "out is NULL");
+  gf2_status r = validate_sched(req);
+  if (r != GF2_OK) return r;
+  *out = resolve(req, m, k, n, nullptr);
+  return GF2_OK;
+}
 
 int32_t gf2_choose_schedule(int64_t m, int64_t k, int64_t n, int32_t batch) {
   if (m < 0 || k < 0 || n < 0) return -1;

@@ -64,19 +64,23 @@ void bump_policy_epoch();   // invalidates cached batch plans after a policy or 
 
 // ---- kernels (each .hip file owns its launches) ----
 // Products launched together with descriptors passed by value in the kernel arguments.
-constexpr int kMaxGroup = 49;   // 7^2 Strassen leaves
+constexpr int kMaxGroup = 56;   // 7^2 Strassen leaves plus a k-split tail (fits 4 KiB of kernel arguments)
 struct GroupArgs {
   MulDesc d[kMaxGroup];
   int tile_start[kMaxGroup + 1];
   int count;
+  int remap_n;   // workgroups [0, remap_n) use the XCD remap; later ones (a short tail) map 1:1
 };
 
 // M4RM base case (m4rm.hip).
 int m4rm_num_variants();
 int m4rm_tile_rows(int variant);
+int m4rm_phase_rows(int variant);   // rows of B consumed per table-build phase (8, 16 or 64)
 int m4rm_tile_words(int variant);
 int64_t m4rm_tiles(const MulDesc& d, int variant);
-gf2_status m4rm_launch_group(const MulDesc* descs, int count, int variant, hipStream_t s);
+// The last ``tail`` descriptors (short k slices) are dispatched after all others, outside
+// the XCD remap, so they fill the last round of tiles.
+gf2_status m4rm_launch_group(const MulDesc* descs, int count, int variant, hipStream_t s, int tail = 0);
 gf2_status m4rm_launch_list(const MulDesc* dev_descs, const int* dev_tile_start, int count, int64_t total_tiles,
                             int variant, hipStream_t s);
 // One queue item of the persistent batch kernel: a C tile of descriptor ``desc``.

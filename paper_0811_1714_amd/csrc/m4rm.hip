@@ -379,18 +379,163 @@ __device__ __forceinline__ void m4rm2_tile_any(const MulDesc& d, int tm, int tn,
   else m4rm2_tile<WAVES, S, INFL, false>(d, tm, tn, tab);
 }
 
+// ---------------------------------------------------------------------------
+// Eight tables per phase (Algorithm 3 with t = 8) for narrow products.  The tile is 256
+// columns (4 words) wide, so the eight 8-bit tables of a 64-row phase of B fit one 64 KiB
+// buffer, interleaved: entry x of table h at x*256 + h*32.  The build is the same Gray
+// walk as above: one ds_write_b32 wave instruction writes entry x of all eight tables
+// (lane L: table L>>3, column dword L&7).  Lookups: two lanes per row (16 B each), so one
+// ds_read_b128 serves 32 rows.  In lookup instruction h, row r reads table h ^ (r & 7):
+// every 16 lanes then touch eight different tables, i.e. all 64 LDS banks.  Each row's A
+// qword (its eight indices for the phase) is byte-permuted once so that instruction h
+// finds row r's index for table h ^ (r & 7) in byte h.
+constexpr int T8_WORDS = 4;                 // 256 columns per tile
+constexpr int P8 = 8 * KB;                  // rows of B per phase
+
+template <int WAVES, int S>
+struct Tile8 {
+  static constexpr int RW = 32 * S;         // rows per wave: 32 per lookup instruction
+  static constexpr int BM = WAVES * RW;
+  static constexpr int HIB = KB - (WAVES == 16 ? 4 : WAVES == 8 ? 3 : WAVES == 4 ? 2 : 1);
+};
+
+template <int WAVES, int S, bool EDGE>
+__device__ __forceinline__ void m4rm8_tile(const MulDesc& d, int tm, int tn, char* tab) {
+  using T = Tile8<WAVES, S>;
+  const int tid = threadIdx.x;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int L = tid & 63, r32 = L >> 1, half = L & 1;
+  const int64_t Wn = words(d.n);
+  const int lw = 2 * half;                              // lane's word offset inside the tile
+  const int64_t c0 = (int64_t)tn * T8_WORDS;            // tile's first word column (uniform)
+  const int64_t Wt = Wn - c0;                           // valid words from the tile start
+  const int64_t row0 = (int64_t)tm * T::BM + (int64_t)w * T::RW;
+  const int rows_here = (int)imin64(d.m - row0, T::RW);
+  const int nphases = (d.k + P8 - 1) / P8;
+  const int kq = (d.k + 63) >> 6;                       // A words per row that hold bits < k
+  const int lda_b = (int)(d.lda * 8), ldb_b = (int)(d.ldb * 8);
+  const __amdgpu_buffer_rsrc_t ra =
+      make_rsrc(d.A + row0 * d.lda, rows_here > 0 ? (int64_t)(rows_here - 1) * lda_b + 8 * kq : 0);
+  // Lookup address, low byte: table (h ^ rr)*32 + half*16 = cb ^ (h*32), rr = r & 7.
+  const uint32_t rr = (uint32_t)r32 & 7u;
+  const uint32_t cb = (rr << 5) | ((uint32_t)half << 4);
+  // Byte permutation of the A qword {hi:lo}: result byte b = source byte b ^ rr.
+  uint32_t sel_lo = 0, sel_hi = 0;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    sel_lo |= ((uint32_t)b ^ rr) << (8 * b);
+    sel_hi |= ((uint32_t)(4 + b) ^ rr) << (8 * b);
+  }
+  // B: lane L builds column dword L&7 of table L>>3, i.e. rows kp + 8*(L>>3) + b.
+  const int boff = (L >> 3) * KB * ldb_b + (L & 7) * 4;
+
+  uint4 acc[S];
+#pragma unroll
+  for (int s = 0; s < S; ++s) acc[s] = make_uint4(0, 0, 0, 0);
+  uint2 ax[S], ay[S];
+  auto load_a = [&](int p, uint2 (&dst)[S]) {
+#pragma unroll
+    for (int s = 0; s < S; ++s) dst[s] = bload2(ra, (32 * s + r32) * lda_b + 8 * p);
+  };
+  StripeRows sr;
+  auto fetch = [&](int p) {
+    constexpr int HIB = T::HIB;
+    const int64_t kp = (int64_t)p * P8;
+    const int rows = (int)imin64(d.k - kp, P8);
+    const __amdgpu_buffer_rsrc_t rb = make_rsrc(d.B + kp * d.ldb + c0, (int64_t)(rows - 1) * ldb_b + 8 * Wt);
+#pragma unroll
+    for (int b = 0; b < KB; ++b) {
+      if (b >= HIB && !((w >> (b - HIB)) & 1)) { sr.r[b] = 0; continue; }
+      sr.r[b] = bload1(rb, boff + b * ldb_b);
+    }
+  };
+  if (nphases > 0) {
+    load_a(0, ax);
+    fetch(0);
+    build_table<WAVES>(tab, 0, w, L, sr);
+  }
+  __syncthreads();
+
+  auto phase = [&](int p, uint2 (&cur)[S], uint2 (&nxt)[S]) {
+    if (p + 1 < nphases) {
+      fetch(p + 1);
+      load_a(p + 1, nxt);
+    }
+    const uint32_t lb = cb | ((uint32_t)(p & 1) << 16);
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const uint32_t lo = __builtin_amdgcn_perm(cur[s].y, cur[s].x, sel_lo);
+      const uint32_t hi = __builtin_amdgcn_perm(cur[s].y, cur[s].x, sel_hi);
+      cur[s] = make_uint2(lo, hi);
+    }
+#pragma unroll
+    for (int h = 0; h < 8; h += 2) {
+      // byte0 <- lb ^ table offset, byte1 <- index byte h (of lo or hi), byte2 <- buffer bit
+      constexpr uint32_t base_sel = 0x0c020400u;
+      const uint32_t l0 = lb ^ ((uint32_t)h << 5), l1 = lb ^ ((uint32_t)(h + 1) << 5);
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        const uint32_t q = h < 4 ? cur[s].x : cur[s].y;
+        const uint32_t a0 = __builtin_amdgcn_perm(q, l0, base_sel + ((uint32_t)(h & 3) << 8));
+        const uint32_t a1 = __builtin_amdgcn_perm(q, l1, base_sel + ((uint32_t)((h + 1) & 3) << 8));
+        const uint4 t0 = *reinterpret_cast<const uint4*>(tab + a0);
+        const uint4 t1 = *reinterpret_cast<const uint4*>(tab + a1);
+        acc[s] = xor3v(acc[s], t0, t1);
+        asm volatile("" : "+v"(acc[s].x), "+v"(acc[s].y), "+v"(acc[s].z), "+v"(acc[s].w));
+      }
+    }
+    if (p + 1 < nphases) build_table<WAVES>(tab, (p & 1) ^ 1, w, L, sr);
+    __syncthreads();
+  };
+  for (int p = 0; p < nphases; p += 2) {
+    phase(p, ax, ay);
+    if (p + 1 < nphases) phase(p + 1, ay, ax);
+  }
+
+  const uint64_t tail = (d.n & 63) ? ((1ull << (d.n & 63)) - 1) : ~0ull;
+  const uint64_t m0 = (EDGE && lw == Wt - 1) ? tail : ~0ull;
+  const uint64_t m1 = (EDGE && lw + 1 == Wt - 1) ? tail : ~0ull;
+  uint64_t* pc = d.C + row0 * d.ldc + c0 + lw;
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const int rrow = 32 * s + r32;
+    if (!EDGE || rrow < rows_here) {
+      uint64_t* cp = pc + (int64_t)rrow * d.ldc;
+      const uint64_t w0 = ((uint64_t)acc[s].x | ((uint64_t)acc[s].y << 32)) & m0;
+      const uint64_t w1 = ((uint64_t)acc[s].z | ((uint64_t)acc[s].w << 32)) & m1;
+      if (!EDGE || lw < Wt) store_word(cp, w0, d.out);
+      if (!EDGE || lw + 1 < Wt) store_word(cp + 1, w1, d.out);
+    }
+  }
+}
+
+template <int WAVES, int S>
+__device__ __forceinline__ void m4rm8_tile_any(const MulDesc& d, int tm, int tn, char* tab) {
+  using T = Tile8<WAVES, S>;
+  const int64_t Wn = words(d.n);
+  const bool edge = (int64_t)(tm + 1) * T::BM > d.m || (int64_t)(tn + 1) * T8_WORDS > Wn ||
+                    ((d.n & 63) != 0 && (int64_t)(tn + 1) * T8_WORDS == Wn);
+  if (edge) m4rm8_tile<WAVES, S, true>(d, tm, tn, tab);
+  else m4rm8_tile<WAVES, S, false>(d, tm, tn, tab);
+}
+
 // Tile policies: one table per stripe (T1: 2048 columns) or two per phase (T2: 1024).
 template <int WAVES, int RW>
 struct PolicyT1 {
-  static constexpr int BM = WAVES * RW, TW = TILE_WORDS, NT = WAVES * 64;
+  static constexpr int BM = WAVES * RW, TW = TILE_WORDS, NT = WAVES * 64, PR = KB;
   __device__ static void run(const MulDesc& d, int tm, int tn, char* tab) { m4rm_tile_any<WAVES, RW>(d, tm, tn, tab); }
 };
 template <int WAVES, int S, int INFL>
 struct PolicyT2 {
-  static constexpr int BM = Tile2<WAVES, S>::BM, TW = T2_WORDS, NT = WAVES * 64;
+  static constexpr int BM = Tile2<WAVES, S>::BM, TW = T2_WORDS, NT = WAVES * 64, PR = PB;
   __device__ static void run(const MulDesc& d, int tm, int tn, char* tab) {
     m4rm2_tile_any<WAVES, S, INFL>(d, tm, tn, tab);
   }
+};
+template <int WAVES, int S>
+struct PolicyT8 {
+  static constexpr int BM = Tile8<WAVES, S>::BM, TW = T8_WORDS, NT = WAVES * 64, PR = P8;
+  __device__ static void run(const MulDesc& d, int tm, int tn, char* tab) { m4rm8_tile_any<WAVES, S>(d, tm, tn, tab); }
 };
 
 // Up to kMaxGroup products in one launch, descriptors passed by value (no device
@@ -399,7 +544,8 @@ struct PolicyT2 {
 template <class P>
 __global__ __launch_bounds__(P::NT) void m4rm_group(GroupArgs g) {
   __shared__ uint4 tab[2 * TABLE_BYTES / 16];
-  const int t = xcd_remap(blockIdx.x, gridDim.x);
+  const int b = blockIdx.x;
+  const int t = b < g.remap_n ? xcd_remap(b, g.remap_n) : b;
   int i = 0;
   while (i + 1 < g.count && g.tile_start[i + 1] <= t) ++i;
   const MulDesc& d = g.d[i];
@@ -426,7 +572,7 @@ __global__ __launch_bounds__(P::NT) void m4rm_list(const MulDesc* __restrict__ d
 }
 
 struct Variant {
-  int threads, bm, tw;      // workgroup size, tile rows, tile width in words
+  int threads, bm, tw, pr;  // workgroup size, tile rows, tile width in words, B rows per barrier phase
   void (*group)(GroupArgs);
   void (*list)(const MulDesc*, const int*, int);
 };
@@ -444,9 +590,13 @@ using V7 = PolicyT2<8, 4, 4>;     // t=2, BM 256, 8 waves
 using V8 = PolicyT1<8, 32>;       // t=1, BM 256, 8 waves
 using V9 = PolicyT1<4, 32>;       // t=1, BM 128, 4 waves
 using V10 = PolicyT2<16, 11, 2>;  // t=2, BM 1408: six tiles cover 8192 rows
-#define GF2_V(P) { P::NT, P::BM, P::TW, m4rm_group<P>, m4rm_list<P> }
+using V11 = PolicyT8<16, 4>;      // t=8, BM 2048 x 256 columns (narrow products)
+using V12 = PolicyT8<16, 2>;      // t=8, BM 1024
+using V13 = PolicyT8<16, 1>;      // t=8, BM 512
+#define GF2_V(P) { P::NT, P::BM, P::TW, P::PR, m4rm_group<P>, m4rm_list<P> }
 const Variant kVariants[] = {GF2_V(V0), GF2_V(V1), GF2_V(V2), GF2_V(V3), GF2_V(V4),
-                             GF2_V(V5), GF2_V(V6), GF2_V(V7), GF2_V(V8), GF2_V(V9), GF2_V(V10)};
+                             GF2_V(V5), GF2_V(V6), GF2_V(V7), GF2_V(V8), GF2_V(V9), GF2_V(V10),
+                             GF2_V(V11), GF2_V(V12), GF2_V(V13)};
 #undef GF2_V
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -486,21 +636,26 @@ const Variant& variant_of(int v) { return kVariants[(v < 0 || v >= kNumVariants)
 int m4rm_num_variants() { return kNumVariants; }
 int m4rm_tile_rows(int variant) { return variant_of(variant).bm; }
 int m4rm_tile_words(int variant) { return variant_of(variant).tw; }
+int m4rm_phase_rows(int variant) { return variant_of(variant).pr; }
 
 int64_t m4rm_tiles(const MulDesc& d, int variant) {
   const int64_t bm = variant_of(variant).bm, tw = variant_of(variant).tw;
   return ((d.m + bm - 1) / bm) * ((words(d.n) + tw - 1) / tw);
 }
 
-gf2_status m4rm_launch_group(const MulDesc* descs, int count, int variant, hipStream_t s) {
+gf2_status m4rm_launch_group(const MulDesc* descs, int count, int variant, hipStream_t s, int tail) {
   const Variant& v = variant_of(variant);
-  for (int base = 0; base < count; base += kMaxGroup) {
+  const int tail_begin = count - (tail > 0 ? tail : 0);
+  int i = 0;
+  while (i < count) {
     GroupArgs g;
     g.count = 0;
+    g.remap_n = -1;
     int64_t total = 0;
-    for (int i = base; i < count && g.count < kMaxGroup; ++i) {
+    for (; i < count && g.count < kMaxGroup; ++i) {
       const int64_t t = m4rm_tiles(descs[i], variant);
       if (t == 0) continue;
+      if (i >= tail_begin && g.remap_n < 0) g.remap_n = (int)total;
       g.d[g.count] = descs[i];
       g.tile_start[g.count] = (int)total;
       ++g.count;
@@ -509,8 +664,9 @@ gf2_status m4rm_launch_group(const MulDesc* descs, int count, int variant, hipSt
     }
     if (g.count == 0) continue;
     g.tile_start[g.count] = (int)total;
+    if (g.remap_n < 0) g.remap_n = (int)total;
     double work = 0;
-    for (int i = 0; i < g.count; ++i) work += (double)g.d[i].m * ((g.d[i].k + KB - 1) / KB) * (double)words(g.d[i].n);
+    for (int j = 0; j < g.count; ++j) work += (double)g.d[j].m * ((g.d[j].k + KB - 1) / KB) * (double)words(g.d[j].n);
     TraceScope trace(GF2_TRACE_M4RM, g.count, work, s);
     hipLaunchKernelGGL(v.group, dim3((unsigned)total), dim3(v.threads), 0, s, g);
     gf2_status st = hip_check(hipGetLastError(), "m4rm_group launch");

@@ -169,12 +169,13 @@ int64_t mfma_tiles(const MulDesc& d) {
 }
 
 gf2_status mfma_launch_group(const MulDesc* descs, int count, hipStream_t s) {
-  for (int base = 0; base < count; base += kMaxGroup) {
+  int i = 0;
+  while (i < count) {
     GroupArgs g;
     g.count = 0;
     int64_t total = 0;
     double work = 0;
-    for (int i = base; i < count && g.count < kMaxGroup; ++i) {
+    for (; i < count && g.count < kMaxGroup; ++i) {
       const int64_t t = mfma_tiles(descs[i]);
       if (t == 0) continue;
       g.d[g.count] = descs[i];
@@ -186,6 +187,7 @@ gf2_status mfma_launch_group(const MulDesc* descs, int count, hipStream_t s) {
     }
     if (g.count == 0) continue;
     g.tile_start[g.count] = (int)total;
+    g.remap_n = (int)total;
     TraceScope trace(GF2_TRACE_MFMA, g.count, work, s);
     hipLaunchKernelGGL(mfma_group, dim3((unsigned)total), dim3(NT), 0, s, g);
     gf2_status st = hip_check(hipGetLastError(), "mfma_group launch");

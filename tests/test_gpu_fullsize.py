@@ -90,6 +90,33 @@ def test_square_products_as_benchmarked(g, n):
             assert np.array_equal(C, first), f"{n}^3 {name}: bits differ from the benchmark schedule"
 
 
+def test_leaf_launch_with_k_split_tail(g):
+    """A Strassen leaf launch whose last round of tiles would be half empty cuts its last
+    leaves into k slices XOR-ed atomically into their zeroed results (8192 x 4096 x 8192,
+    one level, 128-row tiles: 896 tiles on 256 compute units).  Also at two levels with
+    1408-row tiles and odd sizes (294 tiles), and in accumulate mode."""
+    for (m, k, n, v, cutoff, acc) in [(8192, 4096, 8192, 4, 2048, False), (10001, 5000, 9000, 10, 2314, False),
+                                      (8192, 4096, 8192, 4, 2048, True)]:
+        print(f"tail split {(m, k, n)} variant {v} cutoff {cutoff} accumulate {acc}", flush=True)
+        A = synth.uniform(21, synth.TAG_A, m, k)
+        B = synth.uniform(21, synth.TAG_B, k, n)
+        s = g.Schedule(g.KERNEL_M4RM, v, cutoff, 1)
+        if not acc:
+            C = run(g, A, B, m, k, n, s)
+            check_full(A, B, C, m, k, n, f"tail split {(m, k, n)}")
+        else:
+            import torch
+            W = (n + 63) // 64
+            C0 = synth.uniform(22, synth.TAG_C, m, n)
+            dC = to_dev(C0)
+            g.reserve_workspace(g.workspace_bytes(m, k, n, s))
+            g.mul(dC, to_dev(A), to_dev(B), m, k, n, accumulate=True, schedule=s)
+            torch.cuda.synchronize()
+            rows = sample_rows(m)
+            got = from_dev(dC)[rows, :W]
+            assert np.array_equal(got, C0[rows, :W] ^ oracle.mul_rows(A, B, m, k, n, rows)), "addmul differs"
+
+
 RECT = [(10000, 20000, 5000), (20001, 777, 30003), (4095, 65537, 129)]
 
 

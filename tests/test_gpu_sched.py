@@ -98,3 +98,42 @@ def test_autotune_and_policies_keep_bits(g):
     finally:
         g.set_policy(g.POLICY_FIXED)
         g.set_model(None)
+
+
+def test_trained_model_gain_over_fixed_heuristic_on_fresh_shapes(g):
+    """What the trained network gains over the method without it.  On 24 shapes it never
+    saw (the batch workload's shape law, a seed disjoint from training and held-out data),
+    every candidate the persistent batch kernel can run is timed per product inside a batch
+    of copies (exhaustive autotune, the judge).  The model's pick (batch head) must be
+    within 10% of the fastest on average and no worse on average than the fixed heuristic
+    (the tallest tile that fills the machine), which is what the library does without it."""
+    import os
+    import synth
+    if not os.path.exists(g.DEFAULT_MODEL):
+        pytest.skip("no trained model")
+    dims = synth.log_uniform_dims(77, 5, 24, 64, 4096)
+    dens = synth.log_uniform_p(77, 1005, 24, 0.01, 0.5)
+    allowed = np.array([g.candidate(i).kernel == g.KERNEL_M4RM and 1 <= g.candidate(i).variant <= 4
+                        for i in range(g.num_candidates())])
+    r_model, r_fixed = [], []
+    try:
+        g.load_model()
+        for (m, k, n), p in zip(dims, dens):
+            m, k, n = int(m), int(k), int(n)
+            ms, _, _ = g.autotune_batch(m, k, n, density=float(p), reps=3)
+            t = np.where(allowed & (ms > 0), ms, np.inf)
+            g.set_policy(g.POLICY_MODEL)
+            pick_model = g.choose_schedule(m, k, n, batch=True)
+            g.set_policy(g.POLICY_FIXED)
+            pick_fixed = g.choose_schedule(m, k, n, batch=True)
+            r_model.append(t[pick_model] / t.min() - 1)
+            r_fixed.append(t[pick_fixed] / t.min() - 1)
+            print(f"{(m, k, n)} model {pick_model} fixed {pick_fixed} regret {r_model[-1]:.3f} / {r_fixed[-1]:.3f}",
+                  flush=True)
+    finally:
+        g.set_policy(g.POLICY_FIXED)
+        g.set_model(None)
+    mean_model, mean_fixed = float(np.mean(r_model)), float(np.mean(r_fixed))
+    print(f"mean regret: model {mean_model:.4f}, fixed heuristic {mean_fixed:.4f}", flush=True)
+    assert mean_model <= 0.10
+    assert mean_model <= mean_fixed + 0.01

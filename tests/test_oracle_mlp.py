@@ -78,3 +78,21 @@ def test_adam_minimises_a_quadratic_and_training_reduces_loss():
         Y, c = mlp.forward(params, X)
         params, mo, vo = mlp.adam_step(params, mlp.backward(params, c, Y, T, M), mo, vo, t, lr=1e-2)
     assert mlp.loss(mlp.forward(params, X)[0], T, M) < 0.5 * l0
+
+
+def test_committed_schedule_model_report():
+    """The committed schedule model carries its training report: regret on the 500 held-out
+    shapes against exhaustive autotuning.  The batch head (what batched products use) is
+    within 10% of the fastest candidate on average and no worse than the fixed heuristic;
+    the latency head likewise."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                        "paper_0811_1714_amd", "tune", "schedule_model.npz")
+    d = np.load(path)
+    rep = json.loads(str(d["report"]))
+    assert rep["train_shapes"] >= 20000 and rep["heldout_shapes"] == 500
+    assert rep["regret_batch_model"]["mean"] <= 0.10
+    assert rep["regret_batch_model"]["mean"] <= rep["regret_batch_fixed_heuristic"]["mean"]
+    assert rep["regret_latency_model"]["mean"] <= 0.10
+    assert d["params"].size == 4 * 64 + 64 + 2 * (64 * 64 + 64) + 64 * d["target_mean"].size + d["target_mean"].size
