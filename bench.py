@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true", help="run a plain 1 GiB device copy (counter scale)")
     ap.add_argument("--batch", type=int, default=0, help="also time a batch of this many log-uniform products")
     ap.add_argument("--rect", action="store_true", help="time the rectangular and ragged products (library schedule)")
+    ap.add_argument("--configs", action="store_true",
+                    help="1024^3 plain M4RM, and 8K/16K/32K on the library schedule and on the int8 matrix-core base")
     ap.add_argument("--odd-sweep", action="store_true",
                     help="padding vs peeling around 2^14 and at word-misaligned sizes")
     return ap.parse_args()
@@ -131,6 +133,54 @@ def sweep(g):
                 ms, per = time_product(g, dA, dB, dC, n, s, 3, 1)
                 print(json.dumps({"n": n, "variant": v, "cutoff": cutoff, "ms": round(min(per), 4),
                                   "eff_bitops": 2 * n ** 3 / (min(per) * 1e-3)}), flush=True)
+        del dA, dB, dC
+        torch.cuda.empty_cache()
+
+
+def configs_bench(g):
+    """Config 1 (1024^3, M4RM with 8-bit tables, no Strassen: every 16-wave tile height) and
+    config 2 (n = 8192, 16384, 32768: the library's schedule, the same recursion over the int8
+    matrix-core base, and that base without recursion).  Median of 10, HIP events."""
+    import torch
+    import synth
+
+    def med(dA, dB, dC, n, s, reps=10):
+        ws = g.workspace_bytes(n, n, n, s) if s is not None else 0
+        if ws:
+            g.reserve_workspace(ws)
+        for _ in range(2):
+            g.mul(dC, dA, dB, n, n, n, schedule=s)
+        torch.cuda.synchronize()
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+        evs[0].record()
+        for i in range(reps):
+            g.mul(dC, dA, dB, n, n, n, schedule=s)
+            evs[i + 1].record()
+        torch.cuda.synchronize()
+        per = [evs[i].elapsed_time(evs[i + 1]) for i in range(reps)]
+        return float(np.median(per)), float(np.mean(per))
+
+    A = synth.uniform(0, synth.TAG_A, 1024, 1024)
+    B = synth.uniform(0, synth.TAG_B, 1024, 1024)
+    dA, dB = to_dev(A), to_dev(B)
+    dC = torch.empty_like(dA)
+    for v in (0, 10, 1, 2, 3, 4, 11, 12, 13):
+        ms, mean = med(dA, dB, dC, 1024, g.Schedule(g.KERNEL_M4RM, v, 0, 1))
+        print(json.dumps({"config": 1, "n": 1024, "schedule": {"kernel": "m4rm", "variant": v}, "ms": round(ms, 4),
+                          "mean_ms": round(mean, 4), "eff_bitops": 2 * 1024 ** 3 / (ms * 1e-3)}), flush=True)
+    for n in (8192, 16384, 32768):
+        A = synth.uniform(1, synth.TAG_A, n, n)
+        B = synth.uniform(1, synth.TAG_B, n, n)
+        dA, dB = to_dev(A), to_dev(B)
+        dC = torch.empty_like(dA)
+        lib = g.resolve_schedule(n, n, n)
+        runs = [("library", lib), ("mfma-base", g.Schedule(g.KERNEL_MFMA, 0, lib.cutoff, 1)),
+                ("mfma-base, no recursion", g.Schedule(g.KERNEL_MFMA, 0, 0, 1))]
+        for name, s in runs:
+            ms, mean = med(dA, dB, dC, n, s, reps=5 if n == 32768 else 10)
+            print(json.dumps({"config": 2, "n": n, "schedule": name, "kernel": s.kernel, "variant": s.variant,
+                              "cutoff": s.cutoff, "splitk": s.splitk, "ms": round(ms, 4), "mean_ms": round(mean, 4),
+                              "eff_bitops": 2 * n ** 3 / (ms * 1e-3)}), flush=True)
         del dA, dB, dC
         torch.cuda.empty_cache()
 
@@ -298,6 +348,9 @@ def main():
         return
     if args.rect:
         rect_bench(g)
+        return
+    if args.configs:
+        configs_bench(g)
         return
     if args.sweep:
         global SWEEP_N, SWEEP_VARIANTS
