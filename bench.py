@@ -45,6 +45,9 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true", help="run a plain 1 GiB device copy (counter scale)")
     ap.add_argument("--batch", type=int, default=0, help="also time a batch of this many log-uniform products")
     ap.add_argument("--rect", action="store_true", help="time the rectangular and ragged products (library schedule)")
+    ap.add_argument("--ablation", action="store_true",
+                    help="base-case variants of Section 3 at equal size: one table per stripe, t = 2, t = 8")
+    ap.add_argument("--narrow", action="store_true", help="matrix-vector and narrow-B products against the HBM roof")
     ap.add_argument("--configs", action="store_true",
                     help="1024^3 plain M4RM, and 8K/16K/32K on the library schedule and on the int8 matrix-core base")
     ap.add_argument("--odd-sweep", action="store_true",
@@ -181,6 +184,73 @@ def configs_bench(g):
             print(json.dumps({"config": 2, "n": n, "schedule": name, "kernel": s.kernel, "variant": s.variant,
                               "cutoff": s.cutoff, "splitk": s.splitk, "ms": round(ms, 4), "mean_ms": round(mean, 4),
                               "eff_bitops": 2 * n ** 3 / (ms * 1e-3)}), flush=True)
+        del dA, dB, dC
+        torch.cuda.empty_cache()
+
+
+ABLATION = ((5, "one table per 8-row stripe (Alg. 2), 768 x 2048"), (6, "one table, 512 x 2048"),
+            (0, "t = 2 (Alg. 3), 1536 x 1024"), (10, "t = 2, 1408 x 1024"), (1, "t = 2, 1024 x 1024"),
+            (2, "t = 2, 512 x 1024"), (11, "t = 8 (Alg. 3), 2048 x 256"), (12, "t = 8, 1024 x 256"),
+            (13, "t = 8, 512 x 256"))
+
+
+def ablation_bench(g):
+    """Section 3's base-case variants on the GPU at equal size: an n x n product with no
+    Strassen recursion, every tile organisation, 8-bit tables (kappa = 8) throughout."""
+    import torch
+    import synth
+    for n in (8192, 16384):
+        A = synth.uniform(1, synth.TAG_A, n, n)
+        B = synth.uniform(1, synth.TAG_B, n, n)
+        dA, dB = to_dev(A), to_dev(B)
+        dC = torch.empty_like(dA)
+        for v, name in ABLATION:
+            s = g.Schedule(g.KERNEL_M4RM, v, 0, 1)
+            ms, per = time_product(g, dA, dB, dC, n, s, 5, 2)
+            wx = n * (n // 8) * (n // 64)
+            print(json.dumps({"n": n, "variant": v, "tile": name, "ms": round(float(np.median(per)), 4),
+                              "table_row_additions_per_s": wx / (float(np.median(per)) * 1e-3)}), flush=True)
+        del dA, dB, dC
+        torch.cuda.empty_cache()
+
+
+NARROW = ((32768, 32768, 1), (32768, 32768, 8), (32768, 32768, 64), (32768, 32768, 129), (32768, 32768, 256),
+          (4095, 65537, 129), (4095, 65537, 64))
+
+
+def narrow_bench(g):
+    """Matrix-vector and narrow-B products: the popcount kernel (A read once), the eight-table
+    M4RM tile with a k split, the library's choice and the int8 matrix core, against the HBM roof
+    (A + B + C once at 8 TB/s)."""
+    import torch
+    import synth
+    for (m, k, n) in NARROW:
+        A = synth.uniform(1, synth.TAG_A, m, k)
+        B = synth.uniform(1, synth.TAG_B, k, n)
+        dA, dB = to_dev(A), to_dev(B)
+        dC = torch.empty((m, (n + 63) // 64), dtype=torch.int64, device="cuda")
+        hbm = 8.0 * (m * ((k + 63) // 64) + k * ((n + 63) // 64) + m * ((n + 63) // 64))
+        lib = g.resolve_schedule(m, k, n)
+        for name, s in (("library", None), ("popcount", g.Schedule(g.KERNEL_CUBIC, 0, 0, 1)),
+                        ("eight-table, k/32", g.Schedule(g.KERNEL_M4RM, 13, 0, 32)),
+                        ("int8 matrix core", g.Schedule(g.KERNEL_MFMA, 0, 0, 1))):
+            ws = g.workspace_bytes(m, k, n, s) if s is not None else 0
+            if ws:
+                g.reserve_workspace(ws)
+            for _ in range(2):
+                g.mul(dC, dA, dB, m, k, n, schedule=s)
+            torch.cuda.synchronize()
+            evs = [torch.cuda.Event(enable_timing=True) for _ in range(11)]
+            evs[0].record()
+            for i in range(10):
+                g.mul(dC, dA, dB, m, k, n, schedule=s)
+                evs[i + 1].record()
+            torch.cuda.synchronize()
+            ms = float(np.median([evs[i].elapsed_time(evs[i + 1]) for i in range(10)]))
+            print(json.dumps({"m": m, "k": k, "n": n, "schedule": name,
+                              "resolved": None if s is not None else [lib.kernel, lib.variant, lib.cutoff, lib.splitk],
+                              "ms": round(ms, 4), "hbm_roof_ms": round(hbm / 8e12 * 1e3, 4),
+                              "hbm_frac": round(hbm / 8e12 * 1e3 / ms, 3)}), flush=True)
         del dA, dB, dC
         torch.cuda.empty_cache()
 
@@ -351,6 +421,12 @@ def main():
         return
     if args.configs:
         configs_bench(g)
+        return
+    if args.ablation:
+        ablation_bench(g)
+        return
+    if args.narrow:
+        narrow_bench(g)
         return
     if args.sweep:
         global SWEEP_N, SWEEP_VARIANTS
