@@ -519,6 +519,152 @@ __device__ __forceinline__ void m4rm8_tile_any(const MulDesc& d, int tm, int tn,
   else m4rm8_tile<WAVES, S, false>(d, tm, tn, tab);
 }
 
+// ---------------------------------------------------------------------------
+// One-word tiles (n <= 64: matrix-vector and narrow products), 32 tables per phase
+// (Algorithm 3 with t = 32): 256 rows of B per phase, table entries of one 64-bit word.
+// The tables are interleaved by LDS bank: entry x of table j at x*256 + j*8, so table j
+// lives in bank pair j.  Four lanes share a row: lane quarter q loads the row's 8 index
+// bytes of tables 8q..8q+7 for the phase (so one load instruction covers 16 rows x 32
+// contiguous bytes) and looks those tables up; at step s the lane of row slot r reads
+// table 8q + (s ^ (r & 7)), so the 32 lanes of an LDS pass (8 rows x 4 quarters) read
+// 32 distinct bank pairs whatever their indices.  The 8 index bytes are permuted once
+// per phase (byte b moves to b ^ (r & 7)) so that step s finds its index in byte s.
+// The four quarters' partial sums are combined by XOR across lanes at the end.
+// Build: thread (wave w, half h) holds the eight B rows of table j = lane & 31 and walks
+// the Gray code over the low three index bits of entries (2w + h) << 3 | g.
+constexpr int P32 = 32 * KB;                // rows of B per phase
+
+template <int WAVES, int RPT>
+struct Tile32 {
+  static_assert(WAVES == 16, "the build maps 16 waves x 2 halves onto 32 high-bit groups");
+  static constexpr int NT = WAVES * 64;
+  static constexpr int RW = 16 * RPT;       // rows per wave: 16 per slot (4 lanes each)
+  static constexpr int BM = WAVES * RW;
+};
+
+template <int WAVES, int RPT, bool EDGE>
+__device__ __forceinline__ void m4rm32_tile(const MulDesc& d, int tm, int tn, char* tab) {
+  using T = Tile32<WAVES, RPT>;
+  const int tid = threadIdx.x;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int L = tid & 63;
+  const uint32_t lr = (uint32_t)L & 31u;               // build: table of this lane
+  const int q = L & 3, r16 = L >> 2;                    // lookup: quarter and row slot
+  const uint32_t rx = (uint32_t)r16 & 7u;               // table rotation of this row slot
+  const int64_t row0 = (int64_t)tm * T::BM + (int64_t)w * T::RW;
+  const int rows_here = (int)imin64(d.m - row0, T::RW);
+  const int nphases = (d.k + P32 - 1) / P32;
+  const int kq = (d.k + 63) >> 6;                       // A words per row that hold bits < k
+  const int lda_b = (int)(d.lda * 8), ldb_b = (int)(d.ldb * 8);
+  const __amdgpu_buffer_rsrc_t ra =
+      make_rsrc(d.A + row0 * d.lda, rows_here > 0 ? (int64_t)(rows_here - 1) * lda_b + 8 * kq : 0);
+  // Byte permutation of the quarter's 8 index bytes {hi:lo}: result byte b = source b ^ rx.
+  uint32_t sel_lo = 0, sel_hi = 0;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    sel_lo |= ((uint32_t)b ^ rx) << (8 * b);
+    sel_hi |= ((uint32_t)(4 + b) ^ rx) << (8 * b);
+  }
+
+  uint2 acc[RPT], ax[RPT], ay[RPT];
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) acc[i] = make_uint2(0, 0);
+  auto load_a = [&](int p, uint2 (&dst)[RPT]) {
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) dst[i] = bload2(ra, (16 * i + r16) * lda_b + 32 * p + 8 * q);
+  };
+  // B rows of table j = lane & 31 for phase p: rows kp + 8j + b, word tn.
+  uint2 br[KB];
+  auto fetch = [&](int p) {
+    const int64_t kp = (int64_t)p * P32;
+    const int rows = (int)imin64(d.k - kp, P32);
+    const __amdgpu_buffer_rsrc_t rb = make_rsrc(d.B + kp * d.ldb + tn, (int64_t)(rows - 1) * ldb_b + 8);
+#pragma unroll
+    for (int b = 0; b < KB; ++b) br[b] = bload2(rb, (int)(8 * lr + b) * ldb_b);
+  };
+  auto build = [&](int buf) {
+    const uint32_t hb = 2u * (uint32_t)w + ((uint32_t)L >> 5);     // index bits 3..7
+    uint2 v = make_uint2(0, 0);
+#pragma unroll
+    for (int b = 3; b < KB; ++b)
+      if ((hb >> (b - 3)) & 1u) v = make_uint2(v.x ^ br[b].x, v.y ^ br[b].y);
+    char* dst = tab + ((uint32_t)buf << 16) + lr * 8;
+    *reinterpret_cast<uint2*>(dst + (hb << 3) * 256) = v;
+#pragma unroll
+    for (int i = 1; i < 8; ++i) {
+      const int c = __builtin_ctz(i);
+      v = make_uint2(v.x ^ br[c].x, v.y ^ br[c].y);
+      *reinterpret_cast<uint2*>(dst + ((hb << 3) | (uint32_t)(i ^ (i >> 1))) * 256) = v;
+    }
+  };
+  if (nphases > 0) {
+    load_a(0, ax);
+    fetch(0);
+    build(0);
+  }
+  __syncthreads();
+
+  // Lookup address, low byte: (8q + (s ^ rx)) * 8 = base ^ (s * 8), base = (8q + rx) * 8.
+  const uint32_t lb0 = (((uint32_t)q << 3) | rx) << 3;
+  auto phase = [&](int p, uint2 (&cur)[RPT], uint2 (&nxt)[RPT]) {
+    if (p + 1 < nphases) {
+      fetch(p + 1);
+      load_a(p + 1, nxt);
+    }
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const uint32_t lo = __builtin_amdgcn_perm(cur[i].y, cur[i].x, sel_lo);
+      const uint32_t hi = __builtin_amdgcn_perm(cur[i].y, cur[i].x, sel_hi);
+      cur[i] = make_uint2(lo, hi);
+    }
+    const uint32_t lbase = lb0 | ((uint32_t)(p & 1) << 16);
+#pragma unroll
+    for (int st = 0; st < 8; ++st) {
+      const uint32_t lb = lbase ^ ((uint32_t)st << 3);
+      constexpr uint32_t base_sel = 0x0c020400u;
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        const uint32_t src = st < 4 ? cur[i].x : cur[i].y;
+        const uint32_t a = __builtin_amdgcn_perm(src, lb, base_sel + ((uint32_t)(st & 3) << 8));
+        const uint2 t = *reinterpret_cast<const uint2*>(tab + a);
+        acc[i] = make_uint2(acc[i].x ^ t.x, acc[i].y ^ t.y);
+      }
+      // Register fence every two steps: at most 2*RPT lookups in flight.
+      if (st & 1) {
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) asm volatile("" : "+v"(acc[i].x), "+v"(acc[i].y));
+      }
+    }
+    if (p + 1 < nphases) build((p & 1) ^ 1);
+    __syncthreads();
+  };
+  for (int p = 0; p < nphases; p += 2) {
+    phase(p, ax, ay);
+    if (p + 1 < nphases) phase(p + 1, ay, ax);
+  }
+
+  // Combine the four quarters of each row (lanes 4r..4r+3) and let quarter 0 store.
+  const uint64_t tail = ((d.n & 63) && tn == words(d.n) - 1) ? ((1ull << (d.n & 63)) - 1) : ~0ull;
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    uint32_t x = acc[i].x, y = acc[i].y;
+    x ^= (uint32_t)__shfl_xor((int)x, 1);
+    y ^= (uint32_t)__shfl_xor((int)y, 1);
+    x ^= (uint32_t)__shfl_xor((int)x, 2);
+    y ^= (uint32_t)__shfl_xor((int)y, 2);
+    const int r = 16 * i + r16;
+    if (q == 0 && (!EDGE || r < rows_here))
+      store_word(d.C + (row0 + r) * d.ldc + tn, ((uint64_t)x | ((uint64_t)y << 32)) & tail, d.out);
+  }
+}
+
+template <int WAVES, int RPT>
+__device__ __forceinline__ void m4rm32_tile_any(const MulDesc& d, int tm, int tn, char* tab) {
+  using T = Tile32<WAVES, RPT>;
+  if ((int64_t)(tm + 1) * T::BM > d.m) m4rm32_tile<WAVES, RPT, true>(d, tm, tn, tab);
+  else m4rm32_tile<WAVES, RPT, false>(d, tm, tn, tab);
+}
+
 // Tile policies: one table per stripe (T1: 2048 columns) or two per phase (T2: 1024).
 template <int WAVES, int RW>
 struct PolicyT1 {
@@ -531,6 +677,11 @@ struct PolicyT2 {
   __device__ static void run(const MulDesc& d, int tm, int tn, char* tab) {
     m4rm2_tile_any<WAVES, S, INFL>(d, tm, tn, tab);
   }
+};
+template <int WAVES, int RPT>
+struct PolicyT32 {
+  static constexpr int BM = Tile32<WAVES, RPT>::BM, TW = 1, NT = WAVES * 64, PR = P32;
+  __device__ static void run(const MulDesc& d, int tm, int tn, char* tab) { m4rm32_tile_any<WAVES, RPT>(d, tm, tn, tab); }
 };
 template <int WAVES, int S>
 struct PolicyT8 {
@@ -593,10 +744,12 @@ using V10 = PolicyT2<16, 11, 2>;  // t=2, BM 1408: six tiles cover 8192 rows
 using V11 = PolicyT8<16, 4>;      // t=8, BM 2048 x 256 columns (narrow products)
 using V12 = PolicyT8<16, 2>;      // t=8, BM 1024
 using V13 = PolicyT8<16, 1>;      // t=8, BM 512
+using V14 = PolicyT32<16, 4>;     // t=32, BM 1024 x 64 columns (matrix-vector, n <= 64)
+using V15 = PolicyT32<16, 8>;     // t=32, BM 2048
 #define GF2_V(P) { P::NT, P::BM, P::TW, P::PR, m4rm_group<P>, m4rm_list<P> }
 const Variant kVariants[] = {GF2_V(V0), GF2_V(V1), GF2_V(V2), GF2_V(V3), GF2_V(V4),
                              GF2_V(V5), GF2_V(V6), GF2_V(V7), GF2_V(V8), GF2_V(V9), GF2_V(V10),
-                             GF2_V(V11), GF2_V(V12), GF2_V(V13)};
+                             GF2_V(V11), GF2_V(V12), GF2_V(V13), GF2_V(V14), GF2_V(V15)};
 #undef GF2_V
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -644,6 +797,14 @@ int64_t m4rm_tiles(const MulDesc& d, int variant) {
 }
 
 gf2_status m4rm_launch_group(const MulDesc* descs, int count, int variant, hipStream_t s, int tail) {
+  // The one-word tile addresses 256 rows of B per phase with 32-bit offsets: for B rows of
+  // 2^20 words or more the eight-table 512-row tile (same bits) runs instead.
+  if (variant_of(variant).pr == P32)
+    for (int i = 0; i < count; ++i)
+      if (descs[i].ldb >= (int64_t(1) << 20)) {
+        variant = 13;
+        break;
+      }
   const Variant& v = variant_of(variant);
   const int tail_begin = count - (tail > 0 ? tail : 0);
   int i = 0;
