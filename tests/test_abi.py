@@ -127,3 +127,24 @@ def test_peeling_workspace_is_sized_for_the_aligned_core():
     assert peel == core == 15 * 512 * 8 * 8
     assert pad > peel     # padding splits at 513 rows / 9 words
 
+
+
+def test_resolve_schedule_without_gpu():
+    """gf2_resolve_schedule reports what a call would run: the cost-model default for large
+    products (no GPU needed under the fixed policy), requested fields kept, bad input refused."""
+    import paper_0811_1714_amd as g
+    s = g.resolve_schedule(32768, 32768, 32768)
+    assert s.kernel == g.KERNEL_M4RM and s.cutoff > 0 and s.splitk == 1     # Strassen-Winograd over M4RM
+    v = g.resolve_schedule(32768, 32768, 1)
+    assert v.kernel == g.KERNEL_M4RM and v.cutoff == 0 and v.splitk > 1     # matrix-vector: k split
+    assert g.kernel_variants(g.KERNEL_M4RM) > v.variant >= 0
+    req = g.Schedule(g.KERNEL_MFMA, 0, 4096, 1, g.ODD_PEEL)
+    r = g.resolve_schedule(10000, 10000, 10000, req)
+    assert (r.kernel, r.variant, r.cutoff, r.splitk, r.odd) == (g.KERNEL_MFMA, 0, 4096, 1, g.ODD_PEEL)
+    for bad in ((-1, 5, 5, None), (5, 5, 5, g.Schedule(g.KERNEL_M4RM, 999, 0, 1))):
+        try:
+            g.resolve_schedule(*bad)
+        except g.GF2Error as e:
+            assert e.status == 1
+        else:
+            raise AssertionError(f"{bad} accepted")
