@@ -332,8 +332,10 @@ MulDesc make_desc(const View& A, const View& B, uint64_t* C, int64_t ldc, int ou
 // reused leaf after leaf).
 size_t base_scratch_words(const gf2_schedule& s, const std::vector<MulDesc>& ds) {
   size_t w = 0;
-  if (s.kernel == GF2_KERNEL_CUBIC)
+  if (s.kernel == GF2_KERNEL_CUBIC)       // products run one after another
     for (const MulDesc& d : ds) w = std::max(w, cubic_scratch_words(d));
+  if (s.kernel == GF2_KERNEL_MFMA)        // one grouped launch: every product keeps its B transposed
+    for (const MulDesc& d : ds) w += cubic_scratch_words(d);
   return w;
 }
 
@@ -342,7 +344,7 @@ gf2_status run_base(const gf2_schedule& s, const std::vector<MulDesc>& ds, uint6
   if (ds.empty()) return GF2_OK;
   switch (s.kernel) {
     case GF2_KERNEL_MFMA:
-      return mfma_launch_group(ds.data(), (int)ds.size(), st);
+      return mfma_launch_group(ds.data(), (int)ds.size(), scratch, st);
     case GF2_KERNEL_CUBIC:
       for (const MulDesc& d : ds) {
         gf2_status r = cubic_launch(d, scratch, st);
@@ -910,7 +912,7 @@ gf2_status build_batch_plan(const gf2_problem* probs, int64_t count, BatchPlanIm
     for (int c = 0; c < num_candidates(); ++c) allowed[c] = batch_allowed(c) ? 1 : 0;
     if ((r = model_choose_batch(feats, allowed.data(), model_pick)) != GF2_OK) return r;
   }
-  size_t pick = 0;
+  size_t pick = 0, mfma_scratch = 0;
   for (int64_t i = 0; i < count; ++i) {
     const gf2_problem& p = probs[i];
     if (p.schedule >= 0) P.sched[i] = p.schedule;
@@ -922,10 +924,14 @@ gf2_status build_batch_plan(const gf2_problem* probs, int64_t count, BatchPlanIm
       plan_product(pp, nullptr, p.C, p.ldc, p.A, p.lda, p.B, p.ldb, p.m, p.k, p.n, p.accumulate != 0,
                    candidate_fwd(P.sched[i]));
       w = pp.st.ws_words;
-      scratch_words = std::max(scratch_words, pp.scratch_words);
+      // Products on the int8 matrix core share one grouped launch, so their transposed Bs
+      // coexist (sum); other base cases reuse the scratch one product at a time (max).
+      if (candidate_fwd(P.sched[i]).kernel == GF2_KERNEL_MFMA) mfma_scratch += pp.scratch_words;
+      else scratch_words = std::max(scratch_words, pp.scratch_words);
     }
     ws_off[i + 1] = ws_off[i] + w;
   }
+  scratch_words = std::max(scratch_words, mfma_scratch);
   const size_t total = ws_off[count] + scratch_words;
   if (total > 0) {
     if (fault_alloc()) return set_error(GF2_ERR_ALLOC, "injected allocation failure (GF2_FAULT_ALLOC)");

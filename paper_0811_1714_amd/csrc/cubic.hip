@@ -88,16 +88,22 @@ __global__ __launch_bounds__(256) void cubic_kernel(CubicArgs a) {
 
 size_t cubic_scratch_words(const MulDesc& d) { return (size_t)words(d.k) * (size_t)(64 * words(d.n)); }
 
+gf2_status transpose_launch(const MulDesc& d, uint64_t* bt, hipStream_t s) {
+  const int64_t Wn = words(d.n), Wk = words(d.k);
+  if (Wn == 0 || Wk == 0) return GF2_OK;
+  const int64_t blocks = (Wk * Wn + 3) / 4;
+  TraceScope tr(GF2_TRACE_CUBIC, 0, 16.0 * Wk * Wn * 64, s);   // transpose: bytes read + written
+  hipLaunchKernelGGL(transpose_kernel, dim3((unsigned)blocks), dim3(256), 0, s, d.B, d.ldb, (int64_t)d.k, Wn, Wk, bt,
+                     64 * Wn);
+  return hip_check(hipGetLastError(), "transpose launch");
+}
+
 gf2_status cubic_launch(const MulDesc& d, uint64_t* scratch, hipStream_t s) {
   const int64_t Wn = words(d.n), Wk = words(d.k);
   if (d.m == 0 || Wn == 0) return GF2_OK;
   const int64_t ldt = 64 * Wn;
   if (Wk > 0) {
-    const int64_t blocks = (Wk * Wn + 3) / 4;
-    TraceScope tr(GF2_TRACE_CUBIC, 0, 16.0 * Wk * Wn * 64, s);   // transpose: bytes read + written
-    hipLaunchKernelGGL(transpose_kernel, dim3((unsigned)blocks), dim3(256), 0, s, d.B, d.ldb, (int64_t)d.k, Wn, Wk,
-                       scratch, ldt);
-    gf2_status st = hip_check(hipGetLastError(), "transpose launch");
+    gf2_status st = transpose_launch(d, scratch, s);
     if (st != GF2_OK) return st;
   }
   CubicArgs a{d, scratch, ldt};

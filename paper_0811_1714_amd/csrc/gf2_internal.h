@@ -91,13 +91,17 @@ bool m4rm_batchable(int variant);   // can run inside the persistent kernel
 gf2_status m4rm_launch_persistent(const MulDesc* dev_descs, const BatchItem* dev_items, int nitems, int* dev_counter,
                                   int grid, hipStream_t s);
 
-// Exact int8 matrix-core base case (mfma.hip).
+// Exact int8 matrix-core base case (mfma.hip).  Each product's B is first transposed into
+// scratch (cubic_scratch_words each, one after another).
 int64_t mfma_tiles(const MulDesc& d);
-gf2_status mfma_launch_group(const MulDesc* descs, int count, hipStream_t s);
+gf2_status mfma_launch_group(const MulDesc* descs, int count, uint64_t* scratch, hipStream_t s);
 
 // Popcount base case with B transposed into scratch (cubic.hip).
 size_t cubic_scratch_words(const MulDesc& d);
 gf2_status cubic_launch(const MulDesc& d, uint64_t* scratch, hipStream_t s);
+// B (k x n) into bt in k-word-major order: bt[w * 64*words(n) + j] = bits 64w..64w+63 of
+// column j; rows >= k read as zero.
+gf2_status transpose_launch(const MulDesc& d, uint64_t* bt, hipStream_t s);
 
 // Schedule model kernels (mlp.hip).
 int64_t mlp_param_count(int nout);
