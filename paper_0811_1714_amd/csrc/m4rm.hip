@@ -745,7 +745,7 @@ using V11 = PolicyT8<16, 4>;      // t=8, BM 2048 x 256 columns (narrow products
 using V12 = PolicyT8<16, 2>;      // t=8, BM 1024
 using V13 = PolicyT8<16, 1>;      // t=8, BM 512
 using V14 = PolicyT32<16, 4>;     // t=32, BM 1024 x 64 columns (matrix-vector, n <= 64)
-using V15 = PolicyT32<16, 8>;     // t=32, BM 2048
+using V15 = PolicyT32<16, 2>;     // t=32, BM 512
 #define GF2_V(P) { P::NT, P::BM, P::TW, P::PR, m4rm_group<P>, m4rm_list<P> }
 const Variant kVariants[] = {GF2_V(V0), GF2_V(V1), GF2_V(V2), GF2_V(V3), GF2_V(V4),
                              GF2_V(V5), GF2_V(V6), GF2_V(V7), GF2_V(V8), GF2_V(V9), GF2_V(V10),
