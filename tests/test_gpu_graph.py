@@ -1,0 +1,63 @@
+"""Single products under HIP graph capture: once the workspace is reserved, gf2_mul enqueues
+kernels only (no allocation, no host synchronisation, no memset nodes), so a caller may
+capture it.  Each graph is replayed several times with eager work in between, and every
+replay is checked against the oracle."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+import oracle
+import synth
+from gf2_testutil import from_dev, to_dev
+
+
+@pytest.fixture(scope="module")
+def g():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_0811_1714_amd as g
+    g.lib()
+    return g
+
+
+CASES = [
+    ("strassen two levels, 1408-row tiles, k-split tail", 8192, 4096, 8192, (4, 2048, 1)),
+    ("k split into 8 slices", 3000, 9000, 1000, (2, 0, 8)),
+    ("odd sizes, peeling", 2049, 2050, 2051, (1, 512, 1, 1)),
+    ("matrix-vector, one-word tiles", 20000, 20000, 1, (14, 0, 8)),
+]
+
+
+@pytest.mark.parametrize("name,m,k,n,sched", CASES, ids=[c[0] for c in CASES])
+def test_captured_product_replays(g, name, m, k, n, sched):
+    import torch
+    print(f"graph: {name} {(m, k, n)}", flush=True)
+    A = synth.uniform(31, synth.TAG_A, m, k)
+    B = synth.uniform(31, synth.TAG_B, k, n)
+    rows = np.unique(np.linspace(0, m - 1, 48).astype(np.int64))
+    ref = oracle.mul_rows(A, B, m, k, n, rows)
+    dA, dB = to_dev(A), to_dev(B)
+    W = (n + 63) // 64
+    dC = torch.zeros((m, W), dtype=torch.int64, device="cuda")
+    s = g.Schedule(g.KERNEL_M4RM, *sched)
+    g.set_policy(g.POLICY_FIXED)
+    g.reserve_workspace(g.workspace_bytes(m, k, n, s))
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        g.mul(dC, dA, dB, m, k, n, schedule=s, stream=side)      # warm-up outside capture
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=side):
+        g.mul(dC, dA, dB, m, k, n, schedule=s, stream=side)
+    for rep in range(3):
+        dC.fill_(-1)                                               # eager work between replays
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        got = from_dev(dC)
+        assert np.array_equal(got[rows, :W], ref), f"replay {rep} differs from the oracle"
+        if n % 64:
+            assert not np.any(got[:, W - 1] >> np.uint64(n % 64)), "padding bits not zero"
+    del graph
