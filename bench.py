@@ -57,9 +57,9 @@ def parse():
 
 def default_schedule(g, n):
     """Headline schedule, from the MI355X sweep (and the library's own cost model): two
-    Strassen-Winograd levels (cutoff n/4) over the two-table M4RM tile of 1408 rows, which
-    covers each 8192-row leaf of the 32768 product in six tiles."""
-    return g.Schedule(g.KERNEL_M4RM, 10, n // 4 if n >= 8192 else 0, 1)
+    Strassen-Winograd levels (cutoff n/4) over the four-table M4RM tile of 2048 rows x 512
+    columns, which covers each 8192-row leaf of the 32768 product in four row tiles."""
+    return g.Schedule(g.KERNEL_M4RM, 16, n // 4 if n >= 8192 else 0, 1)
 
 
 def m4rm_source_hash():
@@ -191,7 +191,8 @@ def configs_bench(g):
 ABLATION = ((5, "one table per 8-row stripe (Alg. 2), 768 x 2048"), (6, "one table, 512 x 2048"),
             (0, "t = 2 (Alg. 3), 1536 x 1024"), (10, "t = 2, 1408 x 1024"), (1, "t = 2, 1024 x 1024"),
             (2, "t = 2, 512 x 1024"), (11, "t = 8 (Alg. 3), 2048 x 256"), (12, "t = 8, 1024 x 256"),
-            (13, "t = 8, 512 x 256"))
+            (13, "t = 8, 512 x 256"), (16, "t = 4 (Alg. 3), 2048 x 512"), (17, "t = 4, 1536 x 512"),
+            (18, "t = 4, 1024 x 512"))
 
 
 def ablation_bench(g):

@@ -216,7 +216,7 @@ gf2_schedule default_schedule(int64_t m, int64_t k, int64_t n) {
     for (int64_t cutoff : {int64_t(0), mn / 2, mn / 4, mn / 8}) {
       if (cutoff && cutoff < 2048) continue;
       const bool recurse = cutoff > 0 && splittable(m, k, n, cutoff);
-      for (int v : {0, 10, 1, 2, 3, 4, 11, 12, 13, 14, 15}) {
+      for (int v : {0, 10, 1, 2, 3, 4, 11, 12, 13, 14, 15, 16, 17, 18}) {
         if (v >= m4rm_num_variants()) continue;
         for (int sk : {1, 2, 4, 8, 16, 32}) {
           if (sk > 1 && (recurse || words(k) / sk < 16)) continue;

@@ -84,15 +84,31 @@ struct StripeRows {
   uint32_t r[KB];
 };
 
+// Byte offsets of a lane's KB rows of B from the start of a phase of ``phase_rows`` rows,
+// the lane's first row at ``boff``.  A wave needs the rows that select its fixed high index
+// bits (b >= HIB) only where that bit of w is set; the others are pointed one phase further
+// on, past the end of the phase's buffer range, so they load as zero.  The loads then need
+// no branches, which keeps the compiler's count of loads in flight exact (a branch around a
+// load makes it wait for loads it does not need).
+template <int HIB>
+__device__ __forceinline__ void row_offsets(int (&o)[KB], int boff, int ldb_b, int phase_rows, int w) {
+#pragma unroll
+  for (int b = 0; b < KB; ++b) {
+    const bool need = b < HIB || ((w >> (b - HIB)) & 1);
+    o[b] = boff + (b + (need ? 0 : phase_rows)) * ldb_b;
+  }
+}
+
 template <int WAVES>
 __device__ __forceinline__ void load_stripe(StripeRows& sr, const uint64_t* pb, int64_t ldb, int rows,
                                             int64_t row_bytes, int w, int lane) {
   constexpr int HIB = KB - (WAVES == 16 ? 4 : WAVES == 8 ? 3 : WAVES == 4 ? 2 : 1);  // walked rows
 #pragma unroll
   for (int b = 0; b < KB; ++b) {
-    // Rows selecting the wave's fixed high bits are only needed when that bit of w is set.
-    if (b >= HIB && !((w >> (b - HIB)) & 1)) { sr.r[b] = 0; continue; }
-    const __amdgpu_buffer_rsrc_t r = make_rsrc(pb + b * ldb, b < rows ? row_bytes : 0);
+    // Rows selecting the wave's fixed high bits are only needed when that bit of w is set;
+    // the others get an empty range (they load as zero, with no branch around the load).
+    const bool need = b < HIB || ((w >> (b - HIB)) & 1);
+    const __amdgpu_buffer_rsrc_t r = make_rsrc(pb + b * ldb, (b < rows && need) ? row_bytes : 0);
     sr.r[b] = bload1(r, lane * 4);
   }
 }
@@ -290,6 +306,8 @@ __device__ __forceinline__ void m4rm2_tile(const MulDesc& d, int tm, int tn, cha
   const uint32_t swp = hsw ? 0x02030001u : 0x03020100u;
   // B: lane L builds column dword L&31 of table L>>5, i.e. rows kp + 8*(L>>5) + b.
   const int boff = (L >> 5) * KB * ldb_b + (L & 31) * 4;
+  int bo[KB];
+  row_offsets<T::HIB>(bo, boff, ldb_b, PB, w);
 
   uint4 acc[S];
 #pragma unroll
@@ -301,15 +319,11 @@ __device__ __forceinline__ void m4rm2_tile(const MulDesc& d, int tm, int tn, cha
   };
   StripeRows sr;
   auto fetch = [&](int p) {
-    constexpr int HIB = T::HIB;
     const int64_t kp = (int64_t)p * PB;
     const int rows = (int)imin64(d.k - kp, PB);
     const __amdgpu_buffer_rsrc_t rb = make_rsrc(d.B + kp * d.ldb + c0, (int64_t)(rows - 1) * ldb_b + 8 * Wt);
 #pragma unroll
-    for (int b = 0; b < KB; ++b) {
-      if (b >= HIB && !((w >> (b - HIB)) & 1)) { sr.r[b] = 0; continue; }
-      sr.r[b] = bload1(rb, boff + b * ldb_b);
-    }
+    for (int b = 0; b < KB; ++b) sr.r[b] = bload1(rb, bo[b]);
   };
   if (nphases > 0) {
     load_a(0, ax);
@@ -319,7 +333,7 @@ __device__ __forceinline__ void m4rm2_tile(const MulDesc& d, int tm, int tn, cha
   __syncthreads();
 
   auto phase = [&](int p, auto U, const uint32_t (&aw)[S]) {
-    if (p + 1 < nphases) fetch(p + 1);
+    fetch(p + 1);
     const uint32_t buf = (uint32_t)(p & 1) << 16;
     constexpr uint32_t sel0 = 0x0c020400u + ((uint32_t)(2 * decltype(U)::value) << 8);
     constexpr uint32_t sel1 = 0x0c020400u + ((uint32_t)(2 * decltype(U)::value + 1) << 8);
@@ -340,7 +354,7 @@ __device__ __forceinline__ void m4rm2_tile(const MulDesc& d, int tm, int tn, cha
   };
   auto group = [&](int gd, uint32_t (&cur)[S], uint32_t (&nxt)[S]) {
     const int p0 = 2 * gd;
-    if (p0 + 2 < nphases) load_a(gd + 1, nxt);
+    load_a(gd + 1, nxt);
 #pragma unroll
     for (int s = 0; s < S; ++s) cur[s] = __builtin_amdgcn_perm(cur[s], cur[s], swp);
     phase(p0, std::integral_constant<int, 0>{}, cur);
@@ -428,6 +442,8 @@ __device__ __forceinline__ void m4rm8_tile(const MulDesc& d, int tm, int tn, cha
   }
   // B: lane L builds column dword L&7 of table L>>3, i.e. rows kp + 8*(L>>3) + b.
   const int boff = (L >> 3) * KB * ldb_b + (L & 7) * 4;
+  int bo[KB];
+  row_offsets<T::HIB>(bo, boff, ldb_b, P8, w);
 
   uint4 acc[S];
 #pragma unroll
@@ -439,15 +455,11 @@ __device__ __forceinline__ void m4rm8_tile(const MulDesc& d, int tm, int tn, cha
   };
   StripeRows sr;
   auto fetch = [&](int p) {
-    constexpr int HIB = T::HIB;
     const int64_t kp = (int64_t)p * P8;
     const int rows = (int)imin64(d.k - kp, P8);
     const __amdgpu_buffer_rsrc_t rb = make_rsrc(d.B + kp * d.ldb + c0, (int64_t)(rows - 1) * ldb_b + 8 * Wt);
 #pragma unroll
-    for (int b = 0; b < KB; ++b) {
-      if (b >= HIB && !((w >> (b - HIB)) & 1)) { sr.r[b] = 0; continue; }
-      sr.r[b] = bload1(rb, boff + b * ldb_b);
-    }
+    for (int b = 0; b < KB; ++b) sr.r[b] = bload1(rb, bo[b]);
   };
   if (nphases > 0) {
     load_a(0, ax);
@@ -456,14 +468,17 @@ __device__ __forceinline__ void m4rm8_tile(const MulDesc& d, int tm, int tn, cha
   }
   __syncthreads();
 
+  // The next phase's loads are issued unconditionally (past the end they load zeros or
+  // unused stride-gap words, with no branch), and the byte permutation is pinned after the
+  // barrier that ends the previous phase (an empty asm on each qword): hoisted above it, it
+  // would wait there for loads that have only just been issued.
   auto phase = [&](int p, uint2 (&cur)[S], uint2 (&nxt)[S]) {
-    if (p + 1 < nphases) {
-      fetch(p + 1);
-      load_a(p + 1, nxt);
-    }
+    fetch(p + 1);
+    load_a(p + 1, nxt);
     const uint32_t lb = cb | ((uint32_t)(p & 1) << 16);
 #pragma unroll
     for (int s = 0; s < S; ++s) {
+      asm volatile("" : "+v"(cur[s].x), "+v"(cur[s].y));
       const uint32_t lo = __builtin_amdgcn_perm(cur[s].y, cur[s].x, sel_lo);
       const uint32_t hi = __builtin_amdgcn_perm(cur[s].y, cur[s].x, sel_hi);
       cur[s] = make_uint2(lo, hi);
@@ -487,10 +502,12 @@ __device__ __forceinline__ void m4rm8_tile(const MulDesc& d, int tm, int tn, cha
     if (p + 1 < nphases) build_table<WAVES>(tab, (p & 1) ^ 1, w, L, sr);
     __syncthreads();
   };
-  for (int p = 0; p < nphases; p += 2) {
+  int p = 0;
+  for (; p + 1 < nphases; p += 2) {
     phase(p, ax, ay);
-    if (p + 1 < nphases) phase(p + 1, ay, ax);
+    phase(p + 1, ay, ax);
   }
+  if (p < nphases) phase(p, ax, ay);
 
   const uint64_t tail = (d.n & 63) ? ((1ull << (d.n & 63)) - 1) : ~0ull;
   const uint64_t m0 = (EDGE && lw == Wt - 1) ? tail : ~0ull;
@@ -517,6 +534,175 @@ __device__ __forceinline__ void m4rm8_tile_any(const MulDesc& d, int tm, int tn,
                     ((d.n & 63) != 0 && (int64_t)(tn + 1) * T8_WORDS == Wn);
   if (edge) m4rm8_tile<WAVES, S, true>(d, tm, tn, tab);
   else m4rm8_tile<WAVES, S, false>(d, tm, tn, tab);
+}
+
+// ---------------------------------------------------------------------------
+// Four tables per phase (Algorithm 3 with t = 4) on 512-column (8-word) tiles: the four
+// 8-bit tables of a 32-row phase of B fill one 64 KiB buffer, interleaved: entry x of
+// table h at x*256 + h*64.  Per phase and per row this reads as many LDS bytes as the
+// two-table tile (four 64 B half-rows instead of two 128 B ones) and builds a table of
+// the same size, but a phase covers twice the rows of B and a tile holds twice the rows
+// in the same registers (a lane's 16 B accumulator covers a quarter of a 512-bit row):
+// half the table build per product bit, and half the barriers and B fetches per row of B.
+// Build: the Gray walk above; lane L builds column dword L&15 of table L>>4.  Lookups:
+// four lanes per row (16 B each), so one ds_read_b128 serves 16 rows.  In lookup
+// instruction h, row r reads table h ^ (r & 3): the four rows of every 16-lane group hit
+// four different tables, i.e. all 64 banks.  The address is one v_perm of the row's A dword
+// (its four indices for the phase) with a per-lane selector that picks index byte h ^ (r & 3).
+constexpr int T4_WORDS = 8;                 // 512 columns per tile
+constexpr int P4 = 4 * KB;                  // rows of B per phase
+
+template <int WAVES, int S>
+struct Tile4 {
+  static constexpr int RW = 16 * S;         // rows per wave: 16 per lookup instruction
+  static constexpr int BM = WAVES * RW;
+  static constexpr int HIB = KB - (WAVES == 16 ? 4 : WAVES == 8 ? 3 : WAVES == 4 ? 2 : 1);
+};
+
+template <int WAVES, int S, bool EDGE>
+__device__ __forceinline__ void m4rm4_tile(const MulDesc& d, int tm, int tn, char* tab) {
+  using T = Tile4<WAVES, S>;
+  const int tid = threadIdx.x;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int L = tid & 63, r16 = L >> 2, qtr = L & 3;
+  const int64_t Wn = words(d.n);
+  const int lw = 2 * qtr;                               // lane's word offset inside the tile
+  const int64_t c0 = (int64_t)tn * T4_WORDS;            // tile's first word column (uniform)
+  const int64_t Wt = Wn - c0;                           // valid words from the tile start
+  const int64_t row0 = (int64_t)tm * T::BM + (int64_t)w * T::RW;
+  const int rows_here = (int)imin64(d.m - row0, T::RW);
+  const int nphases = (d.k + P4 - 1) / P4;
+  const int kdw = (d.k + 31) >> 5;                      // A dwords per row that hold bits < k
+  const int lda_b = (int)(d.lda * 8), ldb_b = (int)(d.ldb * 8);
+  const __amdgpu_buffer_rsrc_t ra =
+      make_rsrc(d.A + row0 * d.lda, rows_here > 0 ? (int64_t)(rows_here - 1) * lda_b + 4 * kdw : 0);
+  // Lookup address, low byte: table (h ^ rr)*64 + qtr*16 = cb ^ (h*64), rr = r & 3.
+  const uint32_t rr = (uint32_t)r16 & 3u;
+  const uint32_t cb = (rr << 6) | ((uint32_t)qtr << 4);
+  // v_perm selectors of lookup instruction h: byte0 <- low address byte, byte1 <- the row's
+  // index for table h ^ rr (byte h ^ rr of its A dword), byte2 <- buffer bit, byte3 <- 0.
+  uint32_t asel[4];
+#pragma unroll
+  for (int h = 0; h < 4; ++h) asel[h] = 0x0c020400u + ((((uint32_t)h ^ rr)) << 8);
+  // B: lane L builds column dword L&15 of table L>>4, i.e. rows kp + 8*(L>>4) + b, read at
+  // offset boff from a buffer resource per b that starts at row kp + b.  Its range ends with
+  // the phase's last row (rows at or past k read as zero), and is empty for a row that
+  // selects one of the wave's fixed high index bits where that bit of w is clear (such a
+  // row is not needed, and must read as zero).  One offset register serves all eight loads.
+  const int boff = (L >> 4) * KB * ldb_b + (L & 15) * 4;
+
+  uint4 acc[S];
+#pragma unroll
+  for (int s = 0; s < S; ++s) acc[s] = make_uint4(0, 0, 0, 0);
+  // A: every four phases, lane (row slot r, quarter q) loads dword 4c + q of its row for each
+  // slot s, so one load instruction covers 16 rows x 16 contiguous bytes (four phases of
+  // indices) instead of 16 rows x 4 bytes; phase 4c + j then takes dword j from the row's
+  // quarter-j lane with a quad broadcast (DPP).  Chunk c + 1 is loaded at the start of
+  // chunk c, four phases ahead of its use.
+  uint32_t ax[S], ay[S];
+  auto load_chunk = [&](int c, uint32_t (&dst)[S]) {
+#pragma unroll
+    for (int s = 0; s < S; ++s) dst[s] = bload1(ra, (16 * s + r16) * lda_b + 16 * c + 4 * qtr);
+  };
+  StripeRows sr;
+  auto fetch = [&](int p) {
+    const int64_t kp = (int64_t)p * P4;
+    const int rows = (int)imin64(d.k - kp, P4);
+#pragma unroll
+    for (int b = 0; b < KB; ++b) {
+      const bool need = b < T::HIB || ((w >> (b - T::HIB)) & 1);
+      const int64_t nb = need ? (int64_t)(rows - 1 - b) * ldb_b + 8 * Wt : 0;
+      sr.r[b] = bload1(make_rsrc(d.B + (kp + b) * d.ldb + c0, nb), boff);
+    }
+  };
+  if (nphases > 0) {
+    load_chunk(0, ax);
+    fetch(0);
+    build_table<WAVES>(tab, 0, w, L, sr);
+  }
+  __syncthreads();
+
+  // Phase p = 4c + J of chunk c.  The next phase's B rows and, at J = 0, the next chunk of A
+  // are loaded unconditionally: past the end the B range is empty and the A offsets stay
+  // inside the tile's rows (or past the range, reading zero), and what they bring is never
+  // used.  Keeping branches away from the loads lets the compiler wait for exactly the loads
+  // each step needs; B is issued first so the table build waits for it alone.
+  auto phase = [&](int p, auto J, uint32_t (&cur)[S], uint32_t (&nxt)[S]) {
+    constexpr int j = decltype(J)::value;
+    fetch(p + 1);
+    if constexpr (j == 0) load_chunk((p >> 2) + 1, nxt);
+    const uint32_t lb = cb | ((uint32_t)(p & 1) << 16);
+    const uint32_t l0 = lb, l1 = lb ^ 64u, l2 = lb ^ 128u, l3 = lb ^ 192u;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      // The row's four indices for this phase, then its four lookups (one per table).
+      const uint32_t aw = (uint32_t)__builtin_amdgcn_mov_dpp((int)cur[s], j * 0x55, 0xf, 0xf, true);
+      const uint4 t0 = *reinterpret_cast<const uint4*>(tab + __builtin_amdgcn_perm(aw, l0, asel[0]));
+      const uint4 t1 = *reinterpret_cast<const uint4*>(tab + __builtin_amdgcn_perm(aw, l1, asel[1]));
+      const uint4 t2 = *reinterpret_cast<const uint4*>(tab + __builtin_amdgcn_perm(aw, l2, asel[2]));
+      const uint4 t3 = *reinterpret_cast<const uint4*>(tab + __builtin_amdgcn_perm(aw, l3, asel[3]));
+      acc[s] = xor3v(xor3v(acc[s], t0, t1), t2, t3);
+      asm volatile("" : "+v"(acc[s].x), "+v"(acc[s].y), "+v"(acc[s].z), "+v"(acc[s].w));
+    }
+    if (p + 1 < nphases) build_table<WAVES>(tab, (p & 1) ^ 1, w, L, sr);
+    __syncthreads();
+  };
+  constexpr std::integral_constant<int, 0> J0{};
+  constexpr std::integral_constant<int, 1> J1{};
+  constexpr std::integral_constant<int, 2> J2{};
+  constexpr std::integral_constant<int, 3> J3{};
+  auto chunk = [&](int c, uint32_t (&cur)[S], uint32_t (&nxt)[S]) {
+    phase(4 * c, J0, cur, nxt);
+    phase(4 * c + 1, J1, cur, nxt);
+    phase(4 * c + 2, J2, cur, nxt);
+    phase(4 * c + 3, J3, cur, nxt);
+  };
+  // The one to three phases of a last, partial chunk.
+  auto part = [&](int c, uint32_t (&cur)[S], uint32_t (&nxt)[S]) {
+    const int rem = nphases - 4 * c;
+    if (rem > 0) phase(4 * c, J0, cur, nxt);
+    if (rem > 1) phase(4 * c + 1, J1, cur, nxt);
+    if (rem > 2) phase(4 * c + 2, J2, cur, nxt);
+  };
+  // Whole chunks with A alternating between ax and ay, then the partial chunk.
+  const int full = nphases >> 2;
+  int c = 0;
+  for (; c + 1 < full; c += 2) {
+    chunk(c, ax, ay);
+    chunk(c + 1, ay, ax);
+  }
+  if (c < full) {
+    chunk(c, ax, ay);
+    part(c + 1, ay, ax);
+  } else {
+    part(c, ax, ay);
+  }
+
+  const uint64_t tail = (d.n & 63) ? ((1ull << (d.n & 63)) - 1) : ~0ull;
+  const uint64_t m0 = (EDGE && lw == Wt - 1) ? tail : ~0ull;
+  const uint64_t m1 = (EDGE && lw + 1 == Wt - 1) ? tail : ~0ull;
+  uint64_t* pc = d.C + row0 * d.ldc + c0 + lw;
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const int rrow = 16 * s + r16;
+    if (!EDGE || rrow < rows_here) {
+      uint64_t* cp = pc + (int64_t)rrow * d.ldc;
+      const uint64_t w0 = ((uint64_t)acc[s].x | ((uint64_t)acc[s].y << 32)) & m0;
+      const uint64_t w1 = ((uint64_t)acc[s].z | ((uint64_t)acc[s].w << 32)) & m1;
+      if (!EDGE || lw < Wt) store_word(cp, w0, d.out);
+      if (!EDGE || lw + 1 < Wt) store_word(cp + 1, w1, d.out);
+    }
+  }
+}
+
+template <int WAVES, int S>
+__device__ __forceinline__ void m4rm4_tile_any(const MulDesc& d, int tm, int tn, char* tab) {
+  using T = Tile4<WAVES, S>;
+  const int64_t Wn = words(d.n);
+  const bool edge = (int64_t)(tm + 1) * T::BM > d.m || (int64_t)(tn + 1) * T4_WORDS > Wn ||
+                    ((d.n & 63) != 0 && (int64_t)(tn + 1) * T4_WORDS == Wn);
+  if (edge) m4rm4_tile<WAVES, S, true>(d, tm, tn, tab);
+  else m4rm4_tile<WAVES, S, false>(d, tm, tn, tab);
 }
 
 // ---------------------------------------------------------------------------
@@ -669,24 +855,29 @@ __device__ __forceinline__ void m4rm32_tile_any(const MulDesc& d, int tm, int tn
 template <int WAVES, int RW>
 struct PolicyT1 {
   static constexpr int BM = WAVES * RW, TW = TILE_WORDS, NT = WAVES * 64, PR = KB;
-  __device__ static void run(const MulDesc& d, int tm, int tn, char* tab) { m4rm_tile_any<WAVES, RW>(d, tm, tn, tab); }
+  __device__ __forceinline__ static void run(const MulDesc& d, int tm, int tn, char* tab) { m4rm_tile_any<WAVES, RW>(d, tm, tn, tab); }
 };
 template <int WAVES, int S, int INFL>
 struct PolicyT2 {
   static constexpr int BM = Tile2<WAVES, S>::BM, TW = T2_WORDS, NT = WAVES * 64, PR = PB;
-  __device__ static void run(const MulDesc& d, int tm, int tn, char* tab) {
+  __device__ __forceinline__ static void run(const MulDesc& d, int tm, int tn, char* tab) {
     m4rm2_tile_any<WAVES, S, INFL>(d, tm, tn, tab);
   }
 };
 template <int WAVES, int RPT>
 struct PolicyT32 {
   static constexpr int BM = Tile32<WAVES, RPT>::BM, TW = 1, NT = WAVES * 64, PR = P32;
-  __device__ static void run(const MulDesc& d, int tm, int tn, char* tab) { m4rm32_tile_any<WAVES, RPT>(d, tm, tn, tab); }
+  __device__ __forceinline__ static void run(const MulDesc& d, int tm, int tn, char* tab) { m4rm32_tile_any<WAVES, RPT>(d, tm, tn, tab); }
+};
+template <int WAVES, int S>
+struct PolicyT4 {
+  static constexpr int BM = Tile4<WAVES, S>::BM, TW = T4_WORDS, NT = WAVES * 64, PR = P4;
+  __device__ __forceinline__ static void run(const MulDesc& d, int tm, int tn, char* tab) { m4rm4_tile_any<WAVES, S>(d, tm, tn, tab); }
 };
 template <int WAVES, int S>
 struct PolicyT8 {
   static constexpr int BM = Tile8<WAVES, S>::BM, TW = T8_WORDS, NT = WAVES * 64, PR = P8;
-  __device__ static void run(const MulDesc& d, int tm, int tn, char* tab) { m4rm8_tile_any<WAVES, S>(d, tm, tn, tab); }
+  __device__ __forceinline__ static void run(const MulDesc& d, int tm, int tn, char* tab) { m4rm8_tile_any<WAVES, S>(d, tm, tn, tab); }
 };
 
 // Up to kMaxGroup products in one launch, descriptors passed by value (no device
@@ -746,10 +937,14 @@ using V12 = PolicyT8<16, 2>;      // t=8, BM 1024
 using V13 = PolicyT8<16, 1>;      // t=8, BM 512
 using V14 = PolicyT32<16, 4>;     // t=32, BM 1024 x 64 columns (matrix-vector, n <= 64)
 using V15 = PolicyT32<16, 2>;     // t=32, BM 512
+using V16 = PolicyT4<16, 8>;      // t=4, BM 2048 x 512 columns: four tiles cover 8192 rows
+using V17 = PolicyT4<16, 6>;      // t=4, BM 1536
+using V18 = PolicyT4<16, 4>;      // t=4, BM 1024
 #define GF2_V(P) { P::NT, P::BM, P::TW, P::PR, m4rm_group<P>, m4rm_list<P> }
 const Variant kVariants[] = {GF2_V(V0), GF2_V(V1), GF2_V(V2), GF2_V(V3), GF2_V(V4),
                              GF2_V(V5), GF2_V(V6), GF2_V(V7), GF2_V(V8), GF2_V(V9), GF2_V(V10),
-                             GF2_V(V11), GF2_V(V12), GF2_V(V13), GF2_V(V14), GF2_V(V15)};
+                             GF2_V(V11), GF2_V(V12), GF2_V(V13), GF2_V(V14), GF2_V(V15),
+                             GF2_V(V16), GF2_V(V17), GF2_V(V18)};
 #undef GF2_V
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -803,6 +998,14 @@ gf2_status m4rm_launch_group(const MulDesc* descs, int count, int variant, hipSt
     for (int i = 0; i < count; ++i)
       if (descs[i].ldb >= (int64_t(1) << 20)) {
         variant = 13;
+        break;
+      }
+  // The four-table tiles address up to 128 rows of A per wave the same way: for A rows of
+  // 2^20 words or more the 1408-row two-table tile runs instead.
+  if (variant_of(variant).pr == P4)
+    for (int i = 0; i < count; ++i)
+      if (descs[i].lda >= (int64_t(1) << 20)) {
+        variant = 10;
         break;
       }
   const Variant& v = variant_of(variant);

@@ -94,9 +94,10 @@ def test_leaf_launch_with_k_split_tail(g):
     """A Strassen leaf launch whose last round of tiles would be half empty cuts its last
     leaves into k slices XOR-ed atomically into their zeroed results (8192 x 4096 x 8192,
     one level, 128-row tiles: 896 tiles on 256 compute units).  Also at two levels with
-    1408-row tiles and odd sizes (294 tiles), and in accumulate mode."""
+    1408-row tiles and odd sizes (294 tiles), with 2048 x 512 four-table tiles (588 tiles),
+    and in accumulate mode."""
     for (m, k, n, v, cutoff, acc) in [(8192, 4096, 8192, 4, 2048, False), (10001, 5000, 9000, 10, 2314, False),
-                                      (8192, 4096, 8192, 4, 2048, True)]:
+                                      (12000, 6000, 12000, 16, 3000, False), (8192, 4096, 8192, 4, 2048, True)]:
         print(f"tail split {(m, k, n)} variant {v} cutoff {cutoff} accumulate {acc}", flush=True)
         A = synth.uniform(21, synth.TAG_A, m, k)
         B = synth.uniform(21, synth.TAG_B, k, n)
