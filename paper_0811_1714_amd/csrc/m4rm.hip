@@ -43,6 +43,10 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, in
   const int nrec = bytes <= 0 ? 0 : (bytes >= 0x7fffffff ? 0x7fffffff : (int)bytes);
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, nrec, 0x00020000);
 }
+// The same for a range known to fit 31 bits (negative means empty), in 32-bit scalar arithmetic.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc32(const void* base, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, bytes > 0 ? bytes : 0, 0x00020000);
+}
 __device__ __forceinline__ uint2 bload2(__amdgpu_buffer_rsrc_t r, int off) {
   return __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
 }
@@ -605,14 +609,17 @@ __device__ __forceinline__ void m4rm4_tile(const MulDesc& d, int tm, int tn, cha
     for (int s = 0; s < S; ++s) dst[s] = bload1(ra, (16 * s + r16) * lda_b + 16 * c + 4 * qtr);
   };
   StripeRows sr;
+  // Ranges fit 31 bits: at most 31 rows of at most 2^24 bytes plus one row's valid bytes.
+  const int wt_b = 8 * (int)Wt;
   auto fetch = [&](int p) {
     const int64_t kp = (int64_t)p * P4;
-    const int rows = (int)imin64(d.k - kp, P4);
+    const int rows = (int)imin64(d.k - kp, P4);          // > -P4 even past the last phase
+    const int last = (rows - 1) * ldb_b + wt_b;           // range from row kp's start
+    const char* rowp = reinterpret_cast<const char*>(d.B + kp * d.ldb + c0);
 #pragma unroll
     for (int b = 0; b < KB; ++b) {
       const bool need = b < T::HIB || ((w >> (b - T::HIB)) & 1);
-      const int64_t nb = need ? (int64_t)(rows - 1 - b) * ldb_b + 8 * Wt : 0;
-      sr.r[b] = bload1(make_rsrc(d.B + (kp + b) * d.ldb + c0, nb), boff);
+      sr.r[b] = bload1(make_rsrc32(rowp + b * ldb_b, need ? last - b * ldb_b : 0), boff);
     }
   };
   if (nphases > 0) {
