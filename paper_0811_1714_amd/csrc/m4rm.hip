@@ -303,10 +303,16 @@ __device__ __forceinline__ void m4rm2_tile(const MulDesc& d, int tm, int tn, cha
   // A: dword gd of a row holds the indices of phases 2gd (bytes 0, 1) and 2gd+1 (bytes 2, 3).
   const __amdgpu_buffer_rsrc_t ra =
       make_rsrc(d.A + row0 * d.lda, rows_here > 0 ? (int64_t)(rows_here - 1) * lda_b + 4 * kdw : 0);
-  // Odd 8-lane groups read table 1 first: their A dwords get bytes swapped in pairs
-  // (indices 2j and 2j+1 exchanged) and their first lookup goes to the table-1 half.
+  // Odd 8-lane groups read table 1 first: their first lookup takes the table-1 index into
+  // the table-1 half, their second the table-0 index into the table-0 half.
   const uint32_t hsw = (uint32_t)g8 & 1u;
   const uint32_t lb0 = hsw * 128u + (uint32_t)l8 * 16u, lb1 = (hsw ^ 1u) * 128u + (uint32_t)l8 * 16u;
+  // v_perm selectors of the two lookups of phase half U (index bytes 2U and 2U+1 of the A
+  // dword): byte0 <- low address byte, byte1 <- index byte, byte2 <- buffer bit, byte3 <- 0.
+  const uint32_t asel00 = 0x0c020400u + (hsw << 8), asel01 = 0x0c020400u + ((1u - hsw) << 8);
+  const uint32_t asel10 = asel00 + 0x200u, asel11 = asel01 + 0x200u;
+  // Tiles of more than eight slots per lane (no registers to spare) swap the A byte pairs
+  // of odd groups in place instead and load one dword per group.
   const uint32_t swp = hsw ? 0x02030001u : 0x03020100u;
   // B: lane L builds column dword L&31 of table L>>5, i.e. rows kp + 8*(L>>5) + b.
   const int boff = (L >> 5) * KB * ldb_b + (L & 31) * 4;
@@ -316,10 +322,15 @@ __device__ __forceinline__ void m4rm2_tile(const MulDesc& d, int tm, int tn, cha
   uint4 acc[S];
 #pragma unroll
   for (int s = 0; s < S; ++s) acc[s] = make_uint4(0, 0, 0, 0);
+  // A: dword gd of a row serves phases 2gd and 2gd+1.  Every eight phases, lane (row slot r,
+  // chunk lane l) loads dword 4c + (l & 3) of its row for each slot s (both quads of a row's
+  // eight lanes hold the same four dwords), so one load covers 8 rows x 16 contiguous bytes;
+  // group gd = 4c + jj takes dword jj from its quad with a quad broadcast (DPP).  Chunk c + 1
+  // is loaded at the start of chunk c, eight phases ahead of its use.
   uint32_t ax[S], ay[S];
-  auto load_a = [&](int gd, uint32_t (&dst)[S]) {
+  auto load_chunk = [&](int c, uint32_t (&dst)[S]) {
 #pragma unroll
-    for (int s = 0; s < S; ++s) dst[s] = bload1(ra, (8 * s + g8) * lda_b + 4 * gd);
+    for (int s = 0; s < S; ++s) dst[s] = bload1(ra, (8 * s + g8) * lda_b + 16 * c + 4 * (l8 & 3));
   };
   StripeRows sr;
   auto fetch = [&](int p) {
@@ -329,24 +340,34 @@ __device__ __forceinline__ void m4rm2_tile(const MulDesc& d, int tm, int tn, cha
 #pragma unroll
     for (int b = 0; b < KB; ++b) sr.r[b] = bload1(rb, bo[b]);
   };
+  constexpr bool kChunked = S <= 8;
+  auto load_a = [&](int gd, uint32_t (&dst)[S]) {
+#pragma unroll
+    for (int s = 0; s < S; ++s) dst[s] = bload1(ra, (8 * s + g8) * lda_b + 4 * gd);
+  };
   if (nphases > 0) {
-    load_a(0, ax);
+    if constexpr (kChunked) load_chunk(0, ax);
+    else load_a(0, ax);
     fetch(0);
     build_table<WAVES>(tab, 0, w, L, sr);
   }
   __syncthreads();
 
-  auto phase = [&](int p, auto U, const uint32_t (&aw)[S]) {
-    fetch(p + 1);
+  // Lookups of phase p with the A dword of each slot given by ``dword(s)``; U = p & 1 picks
+  // the index bytes.  The next phase's B rows (and, at the start of a chunk, the next chunk
+  // of A) are loaded unconditionally: past the end the B range is empty and the A offsets
+  // stay inside the tile's rows (or past the range, reading zero), and the data is never
+  // used.  Keeping branches away from the loads lets the compiler wait for exactly the loads
+  // each step needs.
+  auto lookups = [&](int p, uint32_t s0sel, uint32_t s1sel, auto dword) {
     const uint32_t buf = (uint32_t)(p & 1) << 16;
-    constexpr uint32_t sel0 = 0x0c020400u + ((uint32_t)(2 * decltype(U)::value) << 8);
-    constexpr uint32_t sel1 = 0x0c020400u + ((uint32_t)(2 * decltype(U)::value + 1) << 8);
 #pragma unroll
     for (int s0 = 0; s0 < S; s0 += INFL) {
 #pragma unroll
       for (int s = s0; s < s0 + INFL && s < S; ++s) {
-        const uint4 t0 = *reinterpret_cast<const uint4*>(tab + __builtin_amdgcn_perm(aw[s], lb0 | buf, sel0));
-        const uint4 t1 = *reinterpret_cast<const uint4*>(tab + __builtin_amdgcn_perm(aw[s], lb1 | buf, sel1));
+        const uint32_t aw = dword(s);
+        const uint4 t0 = *reinterpret_cast<const uint4*>(tab + __builtin_amdgcn_perm(aw, lb0 | buf, s0sel));
+        const uint4 t1 = *reinterpret_cast<const uint4*>(tab + __builtin_amdgcn_perm(aw, lb1 | buf, s1sel));
         acc[s] = xor3v(acc[s], t0, t1);
       }
 #pragma unroll
@@ -356,18 +377,74 @@ __device__ __forceinline__ void m4rm2_tile(const MulDesc& d, int tm, int tn, cha
     if (p + 1 < nphases) build_table<WAVES>(tab, (p & 1) ^ 1, w, L, sr);
     __syncthreads();
   };
-  auto group = [&](int gd, uint32_t (&cur)[S], uint32_t (&nxt)[S]) {
-    const int p0 = 2 * gd;
-    load_a(gd + 1, nxt);
-#pragma unroll
-    for (int s = 0; s < S; ++s) cur[s] = __builtin_amdgcn_perm(cur[s], cur[s], swp);
-    phase(p0, std::integral_constant<int, 0>{}, cur);
-    if (p0 + 1 < nphases) phase(p0 + 1, std::integral_constant<int, 1>{}, cur);
+  // Phase p = 8c + 2jj + U of chunk c (jj, U compile-time).
+  auto phase = [&](int p, auto JJ, auto U, const uint32_t (&cur)[S], uint32_t (&nxt)[S]) {
+    constexpr int jj = decltype(JJ)::value, u = decltype(U)::value;
+    fetch(p + 1);
+    if constexpr (jj == 0 && u == 0) load_chunk((p >> 3) + 1, nxt);
+    lookups(p, u ? asel10 : asel00, u ? asel11 : asel01,
+            [&](int s) { return (uint32_t)__builtin_amdgcn_mov_dpp((int)cur[s], jj * 0x55, 0xf, 0xf, true); });
   };
-  const int ngroups = (nphases + 1) >> 1;
-  for (int gd = 0; gd < ngroups; gd += 2) {
-    group(gd, ax, ay);
-    if (gd + 1 < ngroups) group(gd + 1, ay, ax);
+  using I0 = std::integral_constant<int, 0>;
+  using I1 = std::integral_constant<int, 1>;
+  using I2 = std::integral_constant<int, 2>;
+  using I3 = std::integral_constant<int, 3>;
+  auto chunk = [&](int c, uint32_t (&cur)[S], uint32_t (&nxt)[S]) {
+    const int p = 8 * c;
+    phase(p, I0{}, I0{}, cur, nxt);
+    phase(p + 1, I0{}, I1{}, cur, nxt);
+    phase(p + 2, I1{}, I0{}, cur, nxt);
+    phase(p + 3, I1{}, I1{}, cur, nxt);
+    phase(p + 4, I2{}, I0{}, cur, nxt);
+    phase(p + 5, I2{}, I1{}, cur, nxt);
+    phase(p + 6, I3{}, I0{}, cur, nxt);
+    phase(p + 7, I3{}, I1{}, cur, nxt);
+  };
+  // The one to seven phases of a last, partial chunk: the dword comes from the quad's lane
+  // jj through ds_bpermute (jj known only at run time); speed does not matter here.
+  auto part = [&](int c, const uint32_t (&cur)[S]) {
+    for (int p = 8 * c; p < nphases; ++p) {
+      fetch(p + 1);
+      const int jj = (p >> 1) & 3, u = p & 1;
+      const int src = ((L & ~3) | jj) * 4;
+      lookups(p, u ? asel10 : asel00, u ? asel11 : asel01,
+              [&](int s) { return (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)cur[s]); });
+    }
+  };
+  if constexpr (kChunked) {
+    // Whole chunks with A alternating between ax and ay, then the partial chunk.
+    const int full = nphases >> 3;
+    int c = 0;
+    for (; c + 1 < full; c += 2) {
+      chunk(c, ax, ay);
+      chunk(c + 1, ay, ax);
+    }
+    if (c < full) {
+      chunk(c, ax, ay);
+      part(c + 1, ay);
+    } else {
+      part(c, ax);
+    }
+  } else {
+    // One A dword per group (two phases), loaded a group ahead; byte pairs swapped in place.
+    constexpr uint32_t sel00 = 0x0c020400u, sel01 = 0x0c020500u, sel10 = 0x0c020600u, sel11 = 0x0c020700u;
+    auto group = [&](int gd, uint32_t (&cur)[S], uint32_t (&nxt)[S]) {
+      const int p0 = 2 * gd;
+      load_a(gd + 1, nxt);
+#pragma unroll
+      for (int s = 0; s < S; ++s) cur[s] = __builtin_amdgcn_perm(cur[s], cur[s], swp);
+      fetch(p0 + 1);
+      lookups(p0, sel00, sel01, [&](int s) { return cur[s]; });
+      if (p0 + 1 < nphases) {
+        fetch(p0 + 2);
+        lookups(p0 + 1, sel10, sel11, [&](int s) { return cur[s]; });
+      }
+    };
+    const int ngroups = (nphases + 1) >> 1;
+    for (int gd = 0; gd < ngroups; gd += 2) {
+      group(gd, ax, ay);
+      if (gd + 1 < ngroups) group(gd + 1, ay, ax);
+    }
   }
 
   const uint64_t tail = (d.n & 63) ? ((1ull << (d.n & 63)) - 1) : ~0ull;
@@ -929,7 +1006,7 @@ struct Variant {
 // Variants 1..4 (the two-table tiles of 1024 down to 128 rows) can run inside the
 // persistent batch kernel; with only these the kernel fits 128 VGPRs without spills.
 using V0 = PolicyT2<16, 12, 2>;   // t=2, BM 1536 x 1024 columns
-using V1 = PolicyT2<16, 8, 4>;    // t=2, BM 1024
+using V1 = PolicyT2<16, 8, 2>;    // t=2, BM 1024
 using V2 = PolicyT2<16, 4, 4>;    // t=2, BM 512
 using V3 = PolicyT2<16, 2, 2>;    // t=2, BM 256
 using V4 = PolicyT2<16, 1, 1>;    // t=2, BM 128
