@@ -300,7 +300,7 @@ ODD_SIZES = (16383, 16384, 16385, 16320, 16448, 16000)
 def odd_sweep(g):
     """Odd sizes in Strassen-Winograd: virtual zero padding against peeling, n x n products
     around 2^14 and at sizes that are not multiples of 128.  Two levels for every size (the
-    cutoff n/4 + 128 stops both rules after two halvings), 1408-row tiles."""
+    cutoff n/4 + 128 stops both rules after two halvings), the headline's 2048 x 512 tiles."""
     import torch
     import synth
     for n in ODD_SIZES:
@@ -310,7 +310,7 @@ def odd_sweep(g):
         dC = torch.empty_like(dA)
         outs = {}
         for odd, name in ((g.ODD_PAD, "pad"), (g.ODD_PEEL, "peel")):
-            s = g.Schedule(g.KERNEL_M4RM, 10, n // 4 + 128, 1, odd)
+            s = g.Schedule(g.KERNEL_M4RM, 16, n // 4 + 128, 1, odd)
             ws = g.workspace_bytes(n, n, n, s)
             if ws:
                 g.reserve_workspace(ws)

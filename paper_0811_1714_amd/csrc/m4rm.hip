@@ -688,16 +688,21 @@ __device__ __forceinline__ void m4rm4_tile(const MulDesc& d, int tm, int tn, cha
   StripeRows sr;
   // Ranges fit 31 bits: at most 31 rows of at most 2^24 bytes plus one row's valid bytes.
   const int wt_b = 8 * (int)Wt;
-  auto fetch = [&](int p) {
-    const int64_t kp = (int64_t)p * P4;
-    const int rows = (int)imin64(d.k - kp, P4);          // > -P4 even past the last phase
-    const int last = (rows - 1) * ldb_b + wt_b;           // range from row kp's start
-    const char* rowp = reinterpret_cast<const char*>(d.B + kp * d.ldb + c0);
+  // Phases are fetched in order, so the row pointer and the rows left advance by one phase
+  // per call (no 64-bit multiply per phase).
+  const char* bnext = reinterpret_cast<const char*>(d.B + c0);
+  const int64_t bstep = (int64_t)P4 * ldb_b;
+  int64_t kleft = d.k;
+  auto fetch = [&](int) {
+    const int rows = (int)imin64(kleft, P4);              // > -P4 even past the last phase
+    const int last = (rows - 1) * ldb_b + wt_b;           // range from the phase's first row
 #pragma unroll
     for (int b = 0; b < KB; ++b) {
       const bool need = b < T::HIB || ((w >> (b - T::HIB)) & 1);
-      sr.r[b] = bload1(make_rsrc32(rowp + b * ldb_b, need ? last - b * ldb_b : 0), boff);
+      sr.r[b] = bload1(make_rsrc32(bnext + b * ldb_b, need ? last - b * ldb_b : 0), boff);
     }
+    bnext += bstep;
+    kleft -= P4;
   };
   if (nphases > 0) {
     load_chunk(0, ax);
