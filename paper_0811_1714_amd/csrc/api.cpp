@@ -210,6 +210,12 @@ gf2_schedule default_schedule(int64_t m, int64_t k, int64_t n) {
   gf2_schedule s{};
   s.kernel = GF2_KERNEL_M4RM;
   s.splitk = 1;
+  // At most eight columns of B: the popcount base case streams A once against B's columns
+  // in LDS (bound by reading A from HBM), ahead of any table method.
+  if (cubic_narrow_shape(k, n)) {
+    s.kernel = GF2_KERNEL_CUBIC;
+    return s;
+  }
   const int64_t mn = m < n ? (m < k ? m : k) : (n < k ? n : k);
   if ((double)m * (double)k * (double)n >= 1073741824.0) {
     double best = -1;

@@ -6,6 +6,8 @@
 //
 // Bt is B transposed into k-word-major order: Bt[w*ldt + j] holds bits 64w..64w+63
 // of column j, so that the lanes of a wave (consecutive j) read consecutive words.
+#include <algorithm>
+
 #include "gf2_internal.h"
 
 namespace gf2 {
@@ -84,7 +86,71 @@ __global__ __launch_bounds__(256) void cubic_kernel(CubicArgs a) {
   }
 }
 
+// Narrow B (n <= 8 columns: matrix-vector products and their few-column relatives).  Each
+// wave owns whole rows of A and streams them once: lane l takes words l, l + 64, ... of the
+// row (512 contiguous bytes per load instruction, eight loads in flight per lane), ANDs each
+// with the same word of every column of B, and counts bits; the row's parity per column is
+// the parity of the sum over the wave, one ballot each.  The N columns of B (transposed,
+// zero past k and padded with zeros to a whole number of batches) sit in LDS for the whole
+// block, so A is the only stream from HBM.  Words past the row read as zero through the
+// buffer range check.
+constexpr int kNarrowBatch = 8;                           // loads in flight per lane
+constexpr int64_t kNarrowStep = 64 * kNarrowBatch;        // words of a row per batch
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const void* base, int64_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+
+template <int N>
+__global__ __launch_bounds__(256) void narrow_kernel(CubicArgs a) {
+  extern __shared__ uint64_t cols[];                      // N x Wp words, column j at j*Wp
+  const MulDesc& d = a.d;
+  const int64_t Wk = words(d.k);
+  const int64_t Wp = (Wk + kNarrowStep - 1) / kNarrowStep * kNarrowStep;
+  for (int64_t x = threadIdx.x; x < N * Wp; x += 256) {
+    const int64_t j = x / Wp, w = x - j * Wp;
+    cols[x] = w < Wk ? a.Bt[w * a.ldt + j] : 0ull;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const uint64_t tail = (1ull << d.n) - 1;                // n <= 8
+  for (int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); i < d.m; i += (int64_t)gridDim.x * 4) {
+    const __amdgpu_buffer_rsrc_t ra = row_rsrc(d.A + i * d.lda, Wk * 8);
+    uint32_t cnt[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) cnt[j] = 0;
+    for (int64_t w0 = lane; w0 < Wp; w0 += kNarrowStep) {
+      uint64_t x[kNarrowBatch];
+#pragma unroll
+      for (int u = 0; u < kNarrowBatch; ++u) {
+        const uint2 v = __builtin_bit_cast(uint2, __builtin_amdgcn_raw_buffer_load_b64(ra, (int)((w0 + 64 * u) * 8), 0, 0));
+        x[u] = (uint64_t)v.x | ((uint64_t)v.y << 32);
+      }
+#pragma unroll
+      for (int u = 0; u < kNarrowBatch; ++u)
+#pragma unroll
+        for (int j = 0; j < N; ++j) cnt[j] += (uint32_t)__popcll(x[u] & cols[j * Wp + w0 + 64 * u]);
+    }
+    uint64_t bits = 0;
+#pragma unroll
+    for (int j = 0; j < N; ++j) bits |= (uint64_t)(__popcll(__ballot(cnt[j] & 1)) & 1) << j;
+    if (lane == 0) store_word(d.C + i * d.ldc, bits & tail, d.out);
+  }
+}
+
+constexpr int kNarrowCols = 8;
+constexpr int64_t kNarrowLdsBytes = 65536;
+
+int narrow_width(int n) { return n <= 1 ? 1 : n <= 2 ? 2 : n <= 4 ? 4 : 8; }
+int64_t narrow_padded_words(int64_t k) { return (words(k) + kNarrowStep - 1) / kNarrowStep * kNarrowStep; }
+
 }  // namespace
+
+bool cubic_narrow_shape(int64_t k, int64_t n) {
+  return n >= 1 && n <= kNarrowCols && k >= 1 && (int64_t)narrow_width((int)n) * narrow_padded_words(k) * 8 <= kNarrowLdsBytes;
+}
+
+bool cubic_narrow(const MulDesc& d) { return cubic_narrow_shape(d.k, d.n); }
 
 size_t cubic_scratch_words(const MulDesc& d) { return (size_t)words(d.k) * (size_t)(64 * words(d.n)); }
 
@@ -107,6 +173,19 @@ gf2_status cubic_launch(const MulDesc& d, uint64_t* scratch, hipStream_t s) {
     if (st != GF2_OK) return st;
   }
   CubicArgs a{d, scratch, ldt};
+  if (cubic_narrow(d)) {
+    const int nw = narrow_width(d.n);
+    const size_t lds = (size_t)nw * (size_t)narrow_padded_words(d.k) * 8;
+    const int64_t blocks = std::min<int64_t>((d.m + 3) / 4, 2048);
+    TraceScope tr(GF2_TRACE_CUBIC, 2, (double)d.m * d.n * (double)Wk, s);
+    switch (nw) {
+      case 1: hipLaunchKernelGGL(narrow_kernel<1>, dim3((unsigned)blocks), dim3(256), lds, s, a); break;
+      case 2: hipLaunchKernelGGL(narrow_kernel<2>, dim3((unsigned)blocks), dim3(256), lds, s, a); break;
+      case 4: hipLaunchKernelGGL(narrow_kernel<4>, dim3((unsigned)blocks), dim3(256), lds, s, a); break;
+      default: hipLaunchKernelGGL(narrow_kernel<8>, dim3((unsigned)blocks), dim3(256), lds, s, a); break;
+    }
+    return hip_check(hipGetLastError(), "narrow launch");
+  }
   const int64_t waves = ((d.m + CR - 1) / CR) * Wn;
   TraceScope tr(GF2_TRACE_CUBIC, 1, (double)d.m * d.n * (double)Wk, s);
   hipLaunchKernelGGL(cubic_kernel, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, a);

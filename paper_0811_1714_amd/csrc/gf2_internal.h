@@ -99,6 +99,9 @@ gf2_status mfma_launch_group(const MulDesc* descs, int count, uint64_t* scratch,
 // Popcount base case with B transposed into scratch (cubic.hip).
 size_t cubic_scratch_words(const MulDesc& d);
 gf2_status cubic_launch(const MulDesc& d, uint64_t* scratch, hipStream_t s);
+// True when the popcount base case streams A against n <= 8 columns of B held in LDS.
+bool cubic_narrow(const MulDesc& d);
+bool cubic_narrow_shape(int64_t k, int64_t n);
 // B (k x n) into bt in k-word-major order: bt[w * 64*words(n) + j] = bits 64w..64w+63 of
 // column j; rows >= k read as zero.
 gf2_status transpose_launch(const MulDesc& d, uint64_t* bt, hipStream_t s);

@@ -136,8 +136,10 @@ def test_resolve_schedule_without_gpu():
     s = g.resolve_schedule(32768, 32768, 32768)
     assert s.kernel == g.KERNEL_M4RM and s.cutoff > 0 and s.splitk == 1     # Strassen-Winograd over M4RM
     v = g.resolve_schedule(32768, 32768, 1)
-    assert v.kernel == g.KERNEL_M4RM and v.cutoff == 0 and v.splitk > 1     # matrix-vector: k split
-    assert g.kernel_variants(g.KERNEL_M4RM) > v.variant >= 0
+    assert v.kernel == g.KERNEL_CUBIC and v.cutoff == 0                      # matrix-vector: streamed popcount
+    w = g.resolve_schedule(32768, 32768, 64)
+    assert w.kernel == g.KERNEL_M4RM and w.cutoff == 0 and w.splitk > 1     # one-word tiles, k split
+    assert g.kernel_variants(g.KERNEL_M4RM) > w.variant >= 0
     req = g.Schedule(g.KERNEL_MFMA, 0, 4096, 1, g.ODD_PEEL)
     r = g.resolve_schedule(10000, 10000, 10000, req)
     assert (r.kernel, r.variant, r.cutoff, r.splitk, r.odd) == (g.KERNEL_MFMA, 0, 4096, 1, g.ODD_PEEL)

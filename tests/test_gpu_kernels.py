@@ -51,6 +51,21 @@ def test_cubic_popcount_grid(g, m, k, n):
     run_and_check(g, m, k, n, schedule=S(g.KERNEL_CUBIC), seed=m + 5 * k + 7 * n, lda_pad=2, ldb_pad=1, ldc_pad=1)
 
 
+NARROW_SHAPES = [(1, 1, 1), (3, 64, 2), (1000, 5000, 3), (4097, 129, 8), (300, 70000, 2), (257, 4100, 5),
+                 (64, 131072, 1), (2049, 8193, 4)]
+
+
+@pytest.mark.parametrize("m,k,n", NARROW_SHAPES)
+def test_cubic_narrow_streaming(g, m, k, n):
+    """At most eight columns of B: the popcount base case streams A against B's columns held in
+    LDS.  Ragged k, garbage in every padding, wide strides, both output modes, k slices."""
+    print(f"narrow {(m, k, n)}", flush=True)
+    run_and_check(g, m, k, n, schedule=S(g.KERNEL_CUBIC), seed=m + 3 * k + 11 * n, lda_pad=3, ldb_pad=2, ldc_pad=1)
+    run_and_check(g, m, k, n, schedule=S(g.KERNEL_CUBIC), accumulate=True, seed=m + k + n, ldc_pad=2)
+    if k >= 1024:
+        run_and_check(g, m, k, n, schedule=S(g.KERNEL_CUBIC, 0, 0, 4), seed=m + 2 * k + n)
+
+
 def test_cubic_addmul_splitk_strassen(g):
     print("cubic addmul / split-k / strassen", flush=True)
     run_and_check(g, 300, 700, 500, schedule=S(g.KERNEL_CUBIC), accumulate=True, seed=31, ldc_pad=1)
