@@ -733,8 +733,12 @@ __device__ __forceinline__ void m4rm4_tile(const MulDesc& d, int tm, int tn, cha
       acc[s] = xor3v(xor3v(acc[s], t0, t1), t2, t3);
       asm volatile("" : "+v"(acc[s].x), "+v"(acc[s].y), "+v"(acc[s].z), "+v"(acc[s].w));
     }
+    // Lookups run at a raised wave priority and the table build at the normal one, so waves
+    // still looking up are issued ahead of waves already building (about 1% at 32768^3).
+    __builtin_amdgcn_s_setprio(0);
     if (p + 1 < nphases) build_table<WAVES>(tab, (p & 1) ^ 1, w, L, sr);
     __syncthreads();
+    __builtin_amdgcn_s_setprio(2);
   };
   constexpr std::integral_constant<int, 0> J0{};
   constexpr std::integral_constant<int, 1> J1{};
