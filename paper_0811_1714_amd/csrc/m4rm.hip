@@ -696,10 +696,14 @@ __device__ __forceinline__ void m4rm4_tile(const MulDesc& d, int tm, int tn, cha
   auto fetch = [&](int) {
     const int rows = (int)imin64(kleft, P4);              // > -P4 even past the last phase
     const int last = (rows - 1) * ldb_b + wt_b;           // range from the phase's first row
+    const char* rowp = bnext;                             // row kp + b, and its range
+    int left = last;
 #pragma unroll
     for (int b = 0; b < KB; ++b) {
       const bool need = b < T::HIB || ((w >> (b - T::HIB)) & 1);
-      sr.r[b] = bload1(make_rsrc32(bnext + b * ldb_b, need ? last - b * ldb_b : 0), boff);
+      sr.r[b] = bload1(make_rsrc32(rowp, need ? left : 0), boff);
+      rowp += ldb_b;
+      left -= ldb_b;
     }
     bnext += bstep;
     kleft -= P4;
