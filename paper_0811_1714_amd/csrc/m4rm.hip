@@ -1,6 +1,11 @@
 // M4RM base case for gfx950: the Method of the Four Russians (Section 3 of the
 // paper, Algorithms 1-3) with the Gray-code table build of Section 3.1.
 //
+// Tile families (t tables of 8-bit indices per barrier phase, Algorithm 3): t = 1 on
+// 2048-column tiles, t = 2 on 1024, t = 4 on 512 (the large-product kernel), t = 8 on
+// 256 and t = 32 on one-word tiles.  Each keeps its tables in one 64 KiB LDS buffer per
+// phase, double buffered.  The t = 1 form is described first:
+//
 // Mapping onto a CDNA4 compute unit:
 //  * A workgroup owns a C tile of BM = WAVES*RW rows by 2048 columns (32 words);
 //    the tile lives in VGPRs for the whole k loop and is written once (the row
