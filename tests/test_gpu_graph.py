@@ -27,6 +27,7 @@ CASES = [
     ("k split into 8 slices", 3000, 9000, 1000, (2, 0, 8)),
     ("odd sizes, peeling", 2049, 2050, 2051, (1, 512, 1, 1)),
     ("matrix-vector, one-word tiles", 20000, 20000, 1, (14, 0, 8)),
+    ("four-table tiles, one level", 8192, 8192, 4100, (16, 4096, 1)),
 ]
 
 

@@ -76,6 +76,7 @@ def test_peeling_same_bits_as_padding(g, m, k, n, cutoff):
     peel = run_and_check(g, m, k, n, schedule=M4RM(1, cutoff, odd=1), seed=12)
     assert np.array_equal(pad, peel)
     run_and_check(g, m, k, n, schedule=M4RM(3, cutoff, odd=1), seed=13, accumulate=True, ldc_pad=1, lda_pad=1)
+    run_and_check(g, m, k, n, schedule=M4RM(16, cutoff, odd=1), seed=15, ldb_pad=1)
     import paper_0811_1714_amd as gg
     run_and_check(g, m, k, n, schedule=gg.Schedule(gg.KERNEL_MFMA, 0, cutoff, 1, 1), seed=14, ldb_pad=2)
     run_and_check(g, m, k, n, schedule=gg.Schedule(gg.KERNEL_CUBIC, 0, cutoff, 1, 1), seed=15)
