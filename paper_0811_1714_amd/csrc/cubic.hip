@@ -101,16 +101,29 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const void* base, int
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
 }
 
+// Columns 0..nc-1 of B (n <= 8, one word per row) as bit vectors: word w of column j,
+// at cols[j*Wp + w], holds rows 64w..64w+63; zero past k, up to Wp words.  One wave per
+// word: lane l reads row 64w + l, one ballot per column.
+__global__ __launch_bounds__(256) void narrow_columns_kernel(const uint64_t* __restrict__ B, int64_t ldb, int64_t k,
+                                                             int nc, int64_t Wp, uint64_t* __restrict__ cols) {
+  const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (w >= Wp) return;
+  const int lane = threadIdx.x & 63;
+  const int64_t row = w * 64 + lane;
+  const uint64_t x = row < k ? B[row * ldb] : 0ull;
+  for (int j = 0; j < nc; ++j) {
+    const uint64_t v = __ballot((x >> j) & 1);
+    if (lane == j) cols[j * Wp + w] = v;
+  }
+}
+
 template <int N>
 __global__ __launch_bounds__(256) void narrow_kernel(CubicArgs a) {
   extern __shared__ uint64_t cols[];                      // N x Wp words, column j at j*Wp
   const MulDesc& d = a.d;
   const int64_t Wk = words(d.k);
   const int64_t Wp = (Wk + kNarrowStep - 1) / kNarrowStep * kNarrowStep;
-  for (int64_t x = threadIdx.x; x < N * Wp; x += 256) {
-    const int64_t j = x / Wp, w = x - j * Wp;
-    cols[x] = w < Wk ? a.Bt[w * a.ldt + j] : 0ull;
-  }
+  for (int64_t x = threadIdx.x; x < N * Wp; x += 256) cols[x] = a.Bt[x];
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const uint64_t tail = (1ull << d.n) - 1;                // n <= 8
@@ -152,7 +165,10 @@ bool cubic_narrow_shape(int64_t k, int64_t n) {
 
 bool cubic_narrow(const MulDesc& d) { return cubic_narrow_shape(d.k, d.n); }
 
-size_t cubic_scratch_words(const MulDesc& d) { return (size_t)words(d.k) * (size_t)(64 * words(d.n)); }
+size_t cubic_scratch_words(const MulDesc& d) {
+  if (cubic_narrow(d)) return (size_t)narrow_width(d.n) * (size_t)narrow_padded_words(d.k);
+  return (size_t)words(d.k) * (size_t)(64 * words(d.n));
+}
 
 gf2_status transpose_launch(const MulDesc& d, uint64_t* bt, hipStream_t s) {
   const int64_t Wn = words(d.n), Wk = words(d.k);
@@ -168,14 +184,18 @@ gf2_status cubic_launch(const MulDesc& d, uint64_t* scratch, hipStream_t s) {
   const int64_t Wn = words(d.n), Wk = words(d.k);
   if (d.m == 0 || Wn == 0) return GF2_OK;
   const int64_t ldt = 64 * Wn;
-  if (Wk > 0) {
-    gf2_status st = transpose_launch(d, scratch, s);
-    if (st != GF2_OK) return st;
-  }
-  CubicArgs a{d, scratch, ldt};
   if (cubic_narrow(d)) {
     const int nw = narrow_width(d.n);
-    const size_t lds = (size_t)nw * (size_t)narrow_padded_words(d.k) * 8;
+    const int64_t Wp = narrow_padded_words(d.k);
+    const size_t lds = (size_t)nw * (size_t)Wp * 8;
+    {
+      TraceScope tc(GF2_TRACE_CUBIC, 0, 16.0 * (double)Wp * 64, s);
+      hipLaunchKernelGGL(narrow_columns_kernel, dim3((unsigned)((Wp + 3) / 4)), dim3(256), 0, s, d.B, d.ldb,
+                         (int64_t)d.k, nw, Wp, scratch);
+      gf2_status st = hip_check(hipGetLastError(), "narrow columns launch");
+      if (st != GF2_OK) return st;
+    }
+    CubicArgs a{d, scratch, Wp};
     const int64_t blocks = std::min<int64_t>((d.m + 3) / 4, 2048);
     TraceScope tr(GF2_TRACE_CUBIC, 2, (double)d.m * d.n * (double)Wk, s);
     switch (nw) {
@@ -186,6 +206,11 @@ gf2_status cubic_launch(const MulDesc& d, uint64_t* scratch, hipStream_t s) {
     }
     return hip_check(hipGetLastError(), "narrow launch");
   }
+  if (Wk > 0) {
+    gf2_status st = transpose_launch(d, scratch, s);
+    if (st != GF2_OK) return st;
+  }
+  CubicArgs a{d, scratch, ldt};
   const int64_t waves = ((d.m + CR - 1) / CR) * Wn;
   TraceScope tr(GF2_TRACE_CUBIC, 1, (double)d.m * d.n * (double)Wk, s);
   hipLaunchKernelGGL(cubic_kernel, dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, a);
