@@ -341,7 +341,7 @@ size_t base_scratch_words(const gf2_schedule& s, const std::vector<MulDesc>& ds)
   if (s.kernel == GF2_KERNEL_CUBIC)       // products run one after another
     for (const MulDesc& d : ds) w = std::max(w, cubic_scratch_words(d));
   if (s.kernel == GF2_KERNEL_MFMA)        // one grouped launch: every product keeps its B transposed
-    for (const MulDesc& d : ds) w += cubic_scratch_words(d);
+    for (const MulDesc& d : ds) w += transpose_words(d);
   return w;
 }
 

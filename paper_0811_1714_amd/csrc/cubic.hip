@@ -165,9 +165,11 @@ bool cubic_narrow_shape(int64_t k, int64_t n) {
 
 bool cubic_narrow(const MulDesc& d) { return cubic_narrow_shape(d.k, d.n); }
 
+size_t transpose_words(const MulDesc& d) { return (size_t)words(d.k) * (size_t)(64 * words(d.n)); }
+
 size_t cubic_scratch_words(const MulDesc& d) {
   if (cubic_narrow(d)) return (size_t)narrow_width(d.n) * (size_t)narrow_padded_words(d.k);
-  return (size_t)words(d.k) * (size_t)(64 * words(d.n));
+  return transpose_words(d);
 }
 
 gf2_status transpose_launch(const MulDesc& d, uint64_t* bt, hipStream_t s) {

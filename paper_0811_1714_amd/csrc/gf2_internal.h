@@ -92,12 +92,15 @@ gf2_status m4rm_launch_persistent(const MulDesc* dev_descs, const BatchItem* dev
                                   int grid, hipStream_t s);
 
 // Exact int8 matrix-core base case (mfma.hip).  Each product's B is first transposed into
-// scratch (cubic_scratch_words each, one after another).
+// scratch (transpose_words each, one after another).
 int64_t mfma_tiles(const MulDesc& d);
 gf2_status mfma_launch_group(const MulDesc* descs, int count, uint64_t* scratch, hipStream_t s);
 
 // Popcount base case with B transposed into scratch (cubic.hip).
 size_t cubic_scratch_words(const MulDesc& d);
+// Words of B transposed into 64 x 64 bit blocks (transpose_launch), as the int8 matrix-core
+// base reads it: every product of a grouped launch keeps a slice of this size.
+size_t transpose_words(const MulDesc& d);
 gf2_status cubic_launch(const MulDesc& d, uint64_t* scratch, hipStream_t s);
 // True when the popcount base case streams A against n <= 8 columns of B held in LDS.
 bool cubic_narrow(const MulDesc& d);

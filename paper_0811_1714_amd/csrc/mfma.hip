@@ -210,7 +210,7 @@ gf2_status mfma_launch_group(const MulDesc* descs, int count, uint64_t* scratch,
     if (st != GF2_OK) return st;
     d.B = p;
     d.ldb = 64 * words(d.n);
-    p += cubic_scratch_words(d);
+    p += transpose_words(d);
   }
   descs = bt.data();
   int i = 0;

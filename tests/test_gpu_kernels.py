@@ -66,6 +66,14 @@ def test_cubic_narrow_streaming(g, m, k, n):
         run_and_check(g, m, k, n, schedule=S(g.KERNEL_CUBIC, 0, 0, 4), seed=m + 2 * k + n)
 
 
+def test_mfma_narrow_products_in_one_launch(g):
+    """The int8 base keeps every product's B transposed in its own scratch slice; products of at
+    most eight columns (k slices, peeling fix-ups) must get slices of the transposed size,
+    not of the narrow popcount's."""
+    run_and_check(g, 1000, 9000, 3, schedule=S(g.KERNEL_MFMA, 0, 0, 4), seed=61)
+    run_and_check(g, 2049, 2050, 2051, schedule=g.Schedule(g.KERNEL_MFMA, 0, 512, 1, 1), seed=62, ldb_pad=2)
+
+
 def test_cubic_addmul_splitk_strassen(g):
     print("cubic addmul / split-k / strassen", flush=True)
     run_and_check(g, 300, 700, 500, schedule=S(g.KERNEL_CUBIC), accumulate=True, seed=31, ldc_pad=1)
