@@ -104,7 +104,7 @@ def test_trained_model_gain_over_fixed_heuristic_on_fresh_shapes(g):
     """What the trained network gains over the method without it.  On 24 shapes it never
     saw (the batch workload's shape law, a seed disjoint from training and held-out data),
     every candidate the persistent batch kernel can run is timed per product inside a batch
-    of copies (exhaustive autotune, the judge).  The model's pick (batch head) must be
+    of copies (exhaustive autotune, the yardstick for regret).  The model's pick (batch head) must be
     within 10% of the fastest on average and no worse on average than the fixed heuristic
     (the tallest tile that fills the machine), which is what the library does without it."""
     import os
