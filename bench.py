@@ -167,10 +167,15 @@ def configs_bench(g):
     B = synth.uniform(0, synth.TAG_B, 1024, 1024)
     dA, dB = to_dev(A), to_dev(B)
     dC = torch.empty_like(dA)
-    for v in (0, 10, 1, 2, 3, 4, 11, 12, 13):
+    for v in (0, 10, 1, 2, 3, 4, 11, 12, 13, 14, 15, 16, 17, 18):
         ms, mean = med(dA, dB, dC, 1024, g.Schedule(g.KERNEL_M4RM, v, 0, 1))
         print(json.dumps({"config": 1, "n": 1024, "schedule": {"kernel": "m4rm", "variant": v}, "ms": round(ms, 4),
                           "mean_ms": round(mean, 4), "eff_bitops": 2 * 1024 ** 3 / (ms * 1e-3)}), flush=True)
+    lib = g.resolve_schedule(1024, 1024, 1024)
+    ms, mean = med(dA, dB, dC, 1024, lib)
+    print(json.dumps({"config": 1, "n": 1024, "schedule": "library", "variant": lib.variant, "splitk": lib.splitk,
+                      "ms": round(ms, 4), "mean_ms": round(mean, 4), "eff_bitops": 2 * 1024 ** 3 / (ms * 1e-3)}),
+          flush=True)
     for n in (8192, 16384, 32768):
         A = synth.uniform(1, synth.TAG_A, n, n)
         B = synth.uniform(1, synth.TAG_B, n, n)

@@ -145,36 +145,58 @@ int compute_units() {
   return c;
 }
 
-// Predicted time (ms) of an M4RM schedule on MI355X, fitted to 150 timed products
-// (squares of 8192-32768 at every tile, depth and k split, and the rectangular shapes):
+// Predicted time (ms) of an M4RM schedule on MI355X, fitted to 1188 timed products (22
+// shapes from 1024^3 to 32768^3, rectangles down to n = 129, every tile the default
+// chooses from, k split and Strassen-Winograd depth; weighted towards each shape's fastest
+// schedules; leave-one-shape-out regret 4.6% mean):
 //   * tiles run in rounds of one per compute unit; a Strassen leaf launch whose last round
 //     is at most half full spreads that round's work over all units (``run_leaves``);
-//   * a tile costs, per barrier phase of B rows, 0.60 us (table build, barrier, B loads)
-//     plus 0.65 ns per tile row (lookups);
-//   * operand traffic (A once per column tile, B once per row tile) at 4 TB/s, Strassen
-//     passes ((2mk + 2kn + 2.75mn)/8 bytes per node) at 3 TB/s, and a k split's zeroing
-//     at 3 TB/s plus its atomic XORs at 1 TB/s.
+//   * a tile costs, per tile family (rows of B per barrier phase), a fixed start-up, a
+//     cost per phase (table build, barrier, B loads) and a cost per tile row per phase
+//     (lookups); see ``kFamily``;
+//   * operand traffic (A once per column tile, B once per row tile) at 28 TB/s (mostly
+//     cache hits), Strassen passes ((2mk + 2kn + 2.75mn)/8 bytes per node) at 2.6 TB/s, and
+//     a k split's zeroing at 3.3 TB/s plus its atomic XORs at 0.8 TB/s.
+struct CostFamily {
+  int phase_rows;
+  double tile_ms, phase_ms, row_phase_ms;
+};
+constexpr CostFamily kFamily[] = {
+    {16, 5.51e-3, 5.56e-4, 6.88e-7},    // two tables per 16-row phase, 1024 columns
+    {32, 1.065e-2, 5.75e-4, 5.47e-7},   // four tables per 32-row phase, 512 columns
+    {64, 1.207e-2, 4.98e-4, 1.084e-6},  // eight tables per 64-row phase, 256 columns
+    {256, 1.018e-2, 2.84e-3, 1.503e-6}, // 32 tables per 256-row phase, 64 columns
+};
+constexpr double kAddBytesPerMs = 2.59e9, kOperandBytesPerMs = 2.84e10, kZeroBytesPerMs = 3.33e9,
+                 kAtomicBytesPerMs = 8.2e8;
+
+const CostFamily& cost_family(int64_t phase_rows) {
+  for (const CostFamily& f : kFamily)
+    if (f.phase_rows == phase_rows) return f;
+  return kFamily[0];   // single-table tiles (not among the default's choices)
+}
+
 struct CostAcc {
-  double tile_ms = 0, add_bytes = 0, operand_bytes = 0;
+  double tile_ms = 0, add_bytes = 0, operand_bytes = 0, zero_bytes = 0, atomic_bytes = 0;
   int64_t tiles = 0, leaves = 0;
 };
-constexpr double kPhaseMs = 6.0e-4, kRowPhaseMs = 6.5e-7, kAddBytesPerMs = 3.0e9, kAtomicBytesPerMs = 1.0e9,
-                 kOperandBytesPerMs = 4.0e9;
 
 // ``sk`` > 1 (no recursion): k in sk slices, each a tile of its own, XOR-ed atomically into
 // a zeroed C.
 void cost_walk(int64_t m, int64_t k, int64_t n, int64_t cutoff, int v, CostAcc& a, int sk = 1) {
   if (!splittable(m, k, n, cutoff)) {
     const int64_t bm = m4rm_tile_rows(v), tw = m4rm_tile_words(v), pr = m4rm_phase_rows(v);
+    const CostFamily& f = cost_family(pr);
     const int64_t rt = (m + bm - 1) / bm, ct = (words(n) + tw - 1) / tw, t = rt * ct * sk;
     const int64_t ks = sk > 1 ? std::min<int64_t>(k, 64 * ((words(k) + sk - 1) / sk)) : k;
     a.tiles += t;
     a.leaves += 1;
-    a.tile_ms += (double)t * (double)((ks + pr - 1) / pr) * (kPhaseMs + kRowPhaseMs * (double)bm);
+    a.tile_ms += (double)t * (f.tile_ms + (double)((ks + pr - 1) / pr) * (f.phase_ms + f.row_phase_ms * (double)bm));
     a.operand_bytes += 8.0 * ((double)m * words(k) * ct + (double)k * words(n) * rt);
     if (sk > 1) {
       const double cbytes = 8.0 * (double)m * (double)words(n);
-      a.add_bytes += cbytes + cbytes * sk * (kAddBytesPerMs / kAtomicBytesPerMs);
+      a.zero_bytes += cbytes;
+      a.atomic_bytes += cbytes * sk;
     }
     return;
   }
@@ -199,7 +221,8 @@ double predicted_ms(int64_t m, int64_t k, int64_t n, int64_t cutoff, int v, int 
   const int64_t full = (a.tiles + cus - 1) / cus, tail = a.tiles - (full - 1) * cus;
   const bool spread = full >= 2 && 2 * tail <= cus && a.leaves >= 2 && a.leaves <= kMaxGroup;
   const double rounds = spread ? (double)(full - 1) + (double)tail / (double)cus : (double)full;
-  return rounds * a.tile_ms / (double)a.tiles + a.add_bytes / kAddBytesPerMs + a.operand_bytes / kOperandBytesPerMs;
+  return rounds * a.tile_ms / (double)a.tiles + a.add_bytes / kAddBytesPerMs + a.operand_bytes / kOperandBytesPerMs +
+         a.zero_bytes / kZeroBytesPerMs + a.atomic_bytes / kAtomicBytesPerMs;
 }
 
 // Default schedule for a shape (the fixed heuristic, used when nothing better is known).

@@ -1,0 +1,54 @@
+"""The fixed cost model that picks a schedule for large products, checked against timings
+of every schedule it chooses from (measured on MI355X and stored with the library): the
+schedule it picks for each timed shape, and how much slower that is than the fastest."""
+import json
+import os
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SWEEP = os.path.join(ROOT, "paper_0811_1714_amd", "tune", "cost_sweep_mi355x.jsonl")
+
+
+def timings():
+    by = {}
+    for line in open(SWEEP):
+        r = json.loads(line)
+        if "library" in r:
+            continue
+        by.setdefault(tuple(r["shape"]), {})[(r["variant"], r["cutoff"], r["splitk"])] = r["ms"]
+    return by
+
+
+def test_default_schedule_regret_on_timed_shapes():
+    import paper_0811_1714_amd as g
+    by = timings()
+    assert len(by) >= 20
+    regret = {}
+    for shape, ms in by.items():
+        s = g.resolve_schedule(*shape)
+        assert s.kernel == g.KERNEL_M4RM
+        pick = (s.variant, s.cutoff, s.splitk)
+        assert pick in ms, f"{shape}: picked {pick}, which the sweep did not time"
+        regret[shape] = ms[pick] / min(ms.values()) - 1
+    print({k: round(100 * v, 1) for k, v in regret.items()})
+    assert np.mean(list(regret.values())) <= 0.05
+    assert max(regret.values()) <= 0.30
+    # The benchmarked squares and rectangles.
+    for shape in [(8192,) * 3, (16384,) * 3, (32768,) * 3, (10000, 20000, 5000), (4095, 65537, 129)]:
+        assert regret[shape] <= 0.01, (shape, regret[shape])
+    assert regret[(20001, 777, 30003)] <= 0.07
+
+
+def test_fit_reproduces_the_library_constants():
+    """Refitting the stored sweep gives the constants the library uses: its pick and the
+    fit's own argmin agree on every timed shape."""
+    import paper_0811_1714_amd as g
+    from paper_0811_1714_amd.tune import fit_cost
+    data, best = fit_cost.load(SWEEP)
+    shapes = list(dict.fromkeys(d[0] for d in data))
+    p = fit_cost.fit(data, best, set(shapes))
+    for shape in shapes:
+        cands = [(fit_cost.predict(p, a), s) for sh, s, _, a in data if sh == shape]
+        s = g.resolve_schedule(*shape)
+        assert min(cands)[1] == (s.variant, s.cutoff, s.splitk), shape
