@@ -31,8 +31,8 @@ VALU_WORD_XOR_PEAK = 256 * 64 * 2.4e9   # 64-bit table-row additions/s at one v_
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=32768)
     ap.add_argument("--variant", type=int, default=None)
     ap.add_argument("--cutoff", type=int, default=None)
