@@ -1,0 +1,45 @@
+"""Seeded random cross-checks of the whole product path against the CPU oracle: random
+shapes (log-uniform in [8, 5000]), densities, strides and modes under random schedules
+(any base kernel and tile variant, Strassen-Winograd cutoff, odd-size rule and k split).
+Every result must be bit-exact whatever the schedule."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+from gf2_testutil import run_and_check
+
+
+@pytest.fixture(scope="module")
+def g():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_0811_1714_amd as g
+    g.lib()
+    return g
+
+
+def random_case(rng, g):
+    m, k, n = (int(x) for x in np.exp(rng.uniform(np.log(8), np.log(5000), 3)))
+    u = rng.uniform()
+    kernel = g.KERNEL_M4RM if u < 0.7 else (g.KERNEL_MFMA if u < 0.85 else g.KERNEL_CUBIC)
+    variant = int(rng.integers(g.kernel_variants(kernel))) if kernel == g.KERNEL_M4RM else 0
+    # Cutoffs from min(m, k, n) / 1.4 down to / 8 (one to three levels), at least 64.
+    cutoff = 0 if rng.uniform() < 0.4 else max(64, int(min(m, k, n) / 2 ** rng.uniform(0.5, 3)))
+    splitk = 1 if rng.uniform() < 0.6 else int(rng.integers(2, 9))
+    odd = int(rng.integers(2)) if cutoff else 0
+    return dict(m=m, k=k, n=n, schedule=(kernel, variant, cutoff, splitk, odd),
+                accumulate=bool(rng.integers(2)), p=float(rng.choice([0.5, 0.1, 0.01])),
+                lda_pad=int(rng.integers(3)), ldb_pad=int(rng.integers(3)), ldc_pad=int(rng.integers(3)))
+
+
+@pytest.mark.parametrize("block", range(4))
+def test_random_shapes_and_schedules(g, block):
+    rng = np.random.default_rng(20260 + block)
+    for i in range(16):
+        c = random_case(rng, g)
+        print(f"block {block} case {i}: {c}", flush=True)
+        s = g.Schedule(*c["schedule"])
+        run_and_check(g, c["m"], c["k"], c["n"], schedule=s, accumulate=c["accumulate"], p=c["p"],
+                      seed=1000 * block + i, lda_pad=c["lda_pad"], ldb_pad=c["ldb_pad"], ldc_pad=c["ldc_pad"])
