@@ -1,5 +1,5 @@
 """Seeded random cross-checks of the whole product path against the CPU oracle: random
-shapes (log-uniform in [8, 5000]), densities, strides and modes under random schedules
+shapes (log-uniform in [8, 5000], one in five in [1000, 6000]), densities, strides and modes under random schedules
 (any base kernel and tile variant, Strassen-Winograd cutoff, odd-size rule and k split).
 Every result must be bit-exact whatever the schedule."""
 import numpy as np
@@ -34,12 +34,23 @@ def random_case(rng, g):
                 lda_pad=int(rng.integers(3)), ldb_pad=int(rng.integers(3)), ldc_pad=int(rng.integers(3)))
 
 
-@pytest.mark.parametrize("block", range(4))
+def case(i, g):
+    """Case i: its own generator; one case in five has all three dimensions in [1000, 6000]."""
+    rng = np.random.default_rng(500000 + i)
+    c = random_case(rng, g)
+    if rng.uniform() < 0.2:
+        c["m"], c["k"], c["n"] = (int(x) for x in np.exp(rng.uniform(np.log(1000), np.log(6000), 3)))
+        if c["schedule"][2]:
+            s = list(c["schedule"])
+            s[2] = max(64, int(min(c["m"], c["k"], c["n"]) / 2 ** rng.uniform(0.5, 3)))
+            c["schedule"] = tuple(s)
+    return c
+
+
+@pytest.mark.parametrize("block", range(8))
 def test_random_shapes_and_schedules(g, block):
-    rng = np.random.default_rng(20260 + block)
-    for i in range(16):
-        c = random_case(rng, g)
-        print(f"block {block} case {i}: {c}", flush=True)
-        s = g.Schedule(*c["schedule"])
-        run_and_check(g, c["m"], c["k"], c["n"], schedule=s, accumulate=c["accumulate"], p=c["p"],
-                      seed=1000 * block + i, lda_pad=c["lda_pad"], ldb_pad=c["ldb_pad"], ldc_pad=c["ldc_pad"])
+    for i in range(32 * block, 32 * block + 32):
+        c = case(i, g)
+        print(f"case {i}: {c}", flush=True)
+        run_and_check(g, c["m"], c["k"], c["n"], schedule=g.Schedule(*c["schedule"]), accumulate=c["accumulate"],
+                      p=c["p"], seed=500000 + i, lda_pad=c["lda_pad"], ldb_pad=c["ldb_pad"], ldc_pad=c["ldc_pad"])
