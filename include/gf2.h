@@ -142,7 +142,10 @@ int32_t gf2_batch_plan_schedule(gf2_batch_plan plan, int64_t i);
 
 /* ---- Schedule policy, autotuner, schedule model ----
  * How the library chooses a schedule when the caller gives none:
- *   GF2_POLICY_FIXED    the built-in heuristic (tile height vs table-build cost);
+ *   GF2_POLICY_FIXED    the built-in cost model: the M4RM tile, Strassen-Winograd cutoff and k
+ *                       split of lowest predicted time (tile height against table-build
+ *                       cost, Sections 3.2 and 5), or the streamed popcount for n <= 8;
+ *                       batches use the tallest persistent-kernel tile by the same trade-off;
  *   GF2_POLICY_AUTOTUNE time every candidate once per shape bucket (powers of 2^(1/2)
  *                       of m, k, n), cache the fastest; falls back to FIXED under capture;
  *   GF2_POLICY_MODEL    the schedule model set by gf2_set_model (argmin of its predicted
@@ -200,7 +203,7 @@ gf2_status gf2_set_model(const float* params, int64_t count, const float* norm);
  * schedules the persistent kernel can run). */
 int32_t gf2_choose_schedule(int64_t m, int64_t k, int64_t n, int32_t batch);
 /* The schedule gf2_mul_sched(..., req, ...) runs for a product of this shape under the
- * current policy; req NULL is the library's own choice (for large products the M4RM
+ * current policy; req NULL is the library's own choice (under GF2_POLICY_FIXED the M4RM
  * tile height, Strassen-Winograd cutoff and k split of lowest predicted time, Section 5).
  * Under GF2_POLICY_AUTOTUNE this may time the candidates first.  *out is written on
  * GF2_OK; negative dimensions, a NULL out or an invalid req give GF2_ERR_INVALID_ARG. */

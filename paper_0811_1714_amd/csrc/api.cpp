@@ -4,6 +4,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <cmath>
 #include <cstring>
@@ -125,10 +126,6 @@ gf2_schedule g_override{};
 
 uint64_t tail_of(int64_t cols) { return (cols & 63) ? ((1ull << (cols & 63)) - 1) : ~0ull; }
 
-int64_t tiles_for(int64_t m, int64_t n, int v) {
-  const int64_t bm = m4rm_tile_rows(v), tw = m4rm_tile_words(v);
-  return ((m + bm - 1) / bm) * ((words(n) + tw - 1) / tw);
-}
 
 bool splittable(int64_t m, int64_t k, int64_t n, int64_t cutoff);
 
@@ -145,30 +142,32 @@ int compute_units() {
   return c;
 }
 
-// Predicted time (ms) of an M4RM schedule on MI355X, fitted to 1188 timed products (22
-// shapes from 1024^3 to 32768^3, rectangles down to n = 129, every tile the default
-// chooses from, k split and Strassen-Winograd depth; weighted towards each shape's fastest
-// schedules; leave-one-shape-out regret 4.6% mean):
+// Predicted time (ms) of an M4RM schedule on MI355X, fitted to 2914 timed schedules on 70
+// shapes: 22 from 1024^3 to 32768^3 and rectangles down to n = 129 (every tile the default
+// chooses from, k split and Strassen-Winograd depth), and 48 products below 2^30
+// bit-operations with m, k, n log-uniform in [64, 4096).  The fit weights each shape's
+// schedules within 15% of its fastest six-fold.  Leave-one-shape-out, the schedule it picks
+// is 1.5% slower than the fastest on the small products and 5.1% on the large ones.
 //   * tiles run in rounds of one per compute unit; a Strassen leaf launch whose last round
 //     is at most half full spreads that round's work over all units (``run_leaves``);
 //   * a tile costs, per tile family (rows of B per barrier phase), a fixed start-up, a
 //     cost per phase (table build, barrier, B loads) and a cost per tile row per phase
 //     (lookups); see ``kFamily``;
-//   * operand traffic (A once per column tile, B once per row tile) at 28 TB/s (mostly
-//     cache hits), Strassen passes ((2mk + 2kn + 2.75mn)/8 bytes per node) at 2.6 TB/s, and
-//     a k split's zeroing at 3.3 TB/s plus its atomic XORs at 0.8 TB/s.
+//   * operand traffic (A once per column tile, B once per row tile) at 20 TB/s (mostly
+//     cache hits), Strassen passes ((2mk + 2kn + 2.75mn)/8 bytes per node) at 2.4 TB/s, and
+//     a k split's zeroing at 0.8 TB/s plus its atomic XORs at 1.0 TB/s.
 struct CostFamily {
   int phase_rows;
   double tile_ms, phase_ms, row_phase_ms;
 };
 constexpr CostFamily kFamily[] = {
-    {16, 5.51e-3, 5.56e-4, 6.88e-7},    // two tables per 16-row phase, 1024 columns
-    {32, 1.065e-2, 5.75e-4, 5.47e-7},   // four tables per 32-row phase, 512 columns
-    {64, 1.207e-2, 4.98e-4, 1.084e-6},  // eight tables per 64-row phase, 256 columns
-    {256, 1.018e-2, 2.84e-3, 1.503e-6}, // 32 tables per 256-row phase, 64 columns
+    {16, 1.135e-2, 5.096e-4, 6.589e-7},   // two tables per 16-row phase, 1024 columns
+    {32, 1.354e-2, 5.776e-4, 5.039e-7},   // four tables per 32-row phase, 512 columns
+    {64, 1.093e-2, 6.047e-4, 8.915e-7},   // eight tables per 64-row phase, 256 columns
+    {256, 1.171e-2, 2.349e-3, 1.639e-6},  // 32 tables per 256-row phase, 64 columns
 };
-constexpr double kAddBytesPerMs = 2.59e9, kOperandBytesPerMs = 2.84e10, kZeroBytesPerMs = 3.33e9,
-                 kAtomicBytesPerMs = 8.2e8;
+constexpr double kAddBytesPerMs = 2.376e9, kOperandBytesPerMs = 1.982e10, kZeroBytesPerMs = 7.99e8,
+                 kAtomicBytesPerMs = 9.62e8;
 
 const CostFamily& cost_family(int64_t phase_rows) {
   for (const CostFamily& f : kFamily)
@@ -225,11 +224,11 @@ double predicted_ms(int64_t m, int64_t k, int64_t n, int64_t cutoff, int v, int 
          a.zero_bytes / kZeroBytesPerMs + a.atomic_bytes / kAtomicBytesPerMs;
 }
 
-// Default schedule for a shape (the fixed heuristic, used when nothing better is known).
-// Products of >= 2^30 bit-operations: the M4RM tile height, Strassen-Winograd depth and
-// k split with the lowest predicted time.  Smaller ones: the tallest tile that still
-// gives every compute unit work, and k split when there are too few C tiles to fill them.
-gf2_schedule default_schedule(int64_t m, int64_t k, int64_t n) {
+// Default schedule for a shape (used when no model, tuning result or request says
+// otherwise): products with at most eight columns of B take the streamed popcount; all
+// others the M4RM tile, Strassen-Winograd depth and k split of lowest predicted time.  A
+// k slice keeps at least four words (256 rows) of k.  Results are memoised per shape.
+gf2_schedule default_schedule_uncached(int64_t m, int64_t k, int64_t n) {
   gf2_schedule s{};
   s.kernel = GF2_KERNEL_M4RM;
   s.splitk = 1;
@@ -240,36 +239,40 @@ gf2_schedule default_schedule(int64_t m, int64_t k, int64_t n) {
     return s;
   }
   const int64_t mn = m < n ? (m < k ? m : k) : (n < k ? n : k);
-  if ((double)m * (double)k * (double)n >= 1073741824.0) {
-    double best = -1;
-    for (int64_t cutoff : {int64_t(0), mn / 2, mn / 4, mn / 8}) {
-      if (cutoff && cutoff < 2048) continue;
-      const bool recurse = cutoff > 0 && splittable(m, k, n, cutoff);
-      for (int v : {0, 10, 1, 2, 3, 4, 11, 12, 13, 14, 15, 16, 17, 18}) {
-        if (v >= m4rm_num_variants()) continue;
-        for (int sk : {1, 2, 4, 8, 16, 32}) {
-          if (sk > 1 && (recurse || words(k) / sk < 16)) continue;
-          const double t = predicted_ms(m, k, n, cutoff, v, sk);
-          if (best < 0 || t < best) {
-            best = t;
-            s.variant = v;
-            s.cutoff = (int32_t)cutoff;
-            s.splitk = sk;
-          }
+  double best = -1;
+  for (int64_t cutoff : {int64_t(0), mn / 2, mn / 4, mn / 8}) {
+    if (cutoff && cutoff < 2048) continue;
+    const bool recurse = cutoff > 0 && splittable(m, k, n, cutoff);
+    for (int v : {0, 10, 1, 2, 3, 4, 11, 12, 13, 14, 15, 16, 17, 18}) {
+      if (v >= m4rm_num_variants()) continue;
+      for (int sk : {1, 2, 4, 8, 16, 32}) {
+        if (sk > 1 && (recurse || words(k) / sk < 4)) continue;
+        const double t = predicted_ms(m, k, n, cutoff, v, sk);
+        if (best < 0 || t < best) {
+          best = t;
+          s.variant = v;
+          s.cutoff = (int32_t)cutoff;
+          s.splitk = sk;
         }
       }
     }
-    return s;
   }
-  int v = 3;
-  for (int vi : {0, 1, 2, 3}) {
-    if (tiles_for(m, n, vi) >= 512) { v = vi; break; }
+  return s;
+}
+
+gf2_schedule default_schedule(int64_t m, int64_t k, int64_t n) {
+  static std::mutex mu;
+  static std::map<std::array<int64_t, 3>, gf2_schedule> memo;
+  const std::array<int64_t, 3> key{m, k, n};
+  {
+    std::lock_guard<std::mutex> g(mu);
+    auto it = memo.find(key);
+    if (it != memo.end()) return it->second;
   }
-  s.variant = v;
-  const int64_t tiles = tiles_for(m, n, v);
-  int sk = 1;
-  while (tiles * sk < 512 && k / (64 * (sk * 2)) >= 16 && sk * 2 <= kMaxGroup) sk *= 2;
-  s.splitk = sk;
+  const gf2_schedule s = default_schedule_uncached(m, k, n);
+  std::lock_guard<std::mutex> g(mu);
+  if (memo.size() >= 4096) memo.clear();
+  memo.emplace(key, s);
   return s;
 }
 

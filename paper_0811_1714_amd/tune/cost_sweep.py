@@ -37,9 +37,22 @@ def splittable(m, k, n, cutoff):
     return cutoff > 0 and m > c and k > c and n > c
 
 
-def candidates(m, k, n):
+def small_shapes(count=48, seed=11):
+    """Products below 2^30 bit-operations drawn from the batched workload's law (m, k, n
+    log-uniform in [64, 4096)), plus three fixed squares."""
+    import synth
+    dims = synth.log_uniform_dims(seed, 77, 4 * count, 64, 4096)
+    out = [(512,) * 3, (256,) * 3, (768,) * 3]
+    for m, k, n in dims:
+        if m * k * n < 2 ** 30 and len(out) < count:
+            out.append((int(m), int(k), int(n)))
+    return out
+
+
+def candidates(m, k, n, min_slice_words=16):
     """(variant, cutoff, k split) triples the default considers for the shape: cutoffs of
-    min(m, k, n) / 2, / 4, / 8 of at least 2048, k split only without recursion."""
+    min(m, k, n) / 2, / 4, / 8 of at least 2048, k split only without recursion and with
+    at least ``min_slice_words`` words of k per slice."""
     mn = min(m, k, n)
     out = []
     for c in (0, mn // 2, mn // 4, mn // 8):
@@ -49,7 +62,7 @@ def candidates(m, k, n):
             if m * k * n >= 2 ** 45 and c == 0 and v not in (16, 10):
                 continue                      # no recursion at 32768^3: two tiles suffice
             for sk in ((1,) if c else (1, 2, 4, 8, 16, 32)):
-                if sk > 1 and words(k) // sk < 16:
+                if sk > 1 and words(k) // sk < min_slice_words:
                     continue
                 out.append((v, c, sk))
     return out
@@ -58,6 +71,8 @@ def candidates(m, k, n):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default="cost_sweep.jsonl")
+    ap.add_argument("--small", action="store_true", help="products below 2^30 bit-operations instead")
+    ap.add_argument("--min-slice-words", type=int, default=16)
     args = ap.parse_args()
     import torch
     if not torch.cuda.is_available():
@@ -67,13 +82,13 @@ def main():
     g.lib()
     t0 = time.time()
     with open(args.out, "w") as out:
-        for (m, k, n) in SHAPES:
+        for (m, k, n) in (small_shapes() if args.small else SHAPES):
             A = torch.from_numpy(synth.uniform(1, synth.TAG_A, m, k).view(np.int64)).cuda()
             B = torch.from_numpy(synth.uniform(1, synth.TAG_B, k, n).view(np.int64)).cuda()
             C = torch.empty((m, words(n)), dtype=torch.int64, device="cuda")
             lib = g.resolve_schedule(m, k, n)
-            reps = 3 if m * k * n > 2 ** 42 else 5
-            for cand in [None] + candidates(m, k, n):
+            reps = 3 if m * k * n > 2 ** 42 else (5 if m * k * n > 2 ** 30 else 9)
+            for cand in [None] + candidates(m, k, n, args.min_slice_words):
                 s = None if cand is None else g.Schedule(g.KERNEL_M4RM, cand[0], cand[1], cand[2])
                 ws = g.workspace_bytes(m, k, n, s)
                 if ws:

@@ -16,7 +16,8 @@ k split) of an m x k by k x n product:
 The fit minimises the log error of the predicted time, weighted six-fold on each shape's
 schedules within 15% of its fastest, so the model is sharpest where the choice is made.
 
-    python -m paper_0811_1714_amd.tune.fit_cost paper_0811_1714_amd/tune/cost_sweep_mi355x.jsonl [--cv]
+    python -m paper_0811_1714_amd.tune.fit_cost paper_0811_1714_amd/tune/cost_sweep_mi355x.jsonl \
+        paper_0811_1714_amd/tune/cost_sweep_small_mi355x.jsonl [--cv]
 """
 import argparse
 import collections
@@ -91,8 +92,8 @@ def predict(p, a):
             + a["zero"] / (p[14] * 1e6) + a["atom"] / (p[15] * 1e6))
 
 
-def load(path):
-    rows = [json.loads(line) for line in open(path)]
+def load(*paths):
+    rows = [json.loads(line) for path in paths for line in open(path)]
     data = [(tuple(r["shape"]), (r["variant"], r["cutoff"], r["splitk"]), r["ms"]) for r in rows if "library" not in r]
     best = collections.defaultdict(lambda: math.inf)
     for sh, _, ms in data:
@@ -120,10 +121,10 @@ def regret(data, best, p, shape):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("sweep")
+    ap.add_argument("sweep", nargs="+")
     ap.add_argument("--cv", action="store_true", help="also leave-one-shape-out regret")
     args = ap.parse_args()
-    data, best = load(args.sweep)
+    data, best = load(*args.sweep)
     shapes = list(dict.fromkeys(d[0] for d in data))
     p = fit(data, best, set(shapes))
     for i, f in enumerate(FAMILIES):
