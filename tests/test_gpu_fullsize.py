@@ -183,3 +183,17 @@ def test_batch_4096_log_uniform(g):
     finally:
         g.set_policy(g.POLICY_FIXED)
         g.set_model(None)
+
+
+def test_largest_square_65536(g):
+    """Twice the headline size: 65536 x 65536 operands (512 MiB each) under the library's own
+    schedule (three Strassen-Winograd levels, 343 leaves in several grouped launches), checked
+    like the benchmarked sizes."""
+    n = 65536
+    A = synth.uniform(1, synth.TAG_A, n, n)
+    B = synth.uniform(1, synth.TAG_B, n, n)
+    s = g.resolve_schedule(n, n, n)
+    print(f"n={n} library schedule kernel {s.kernel} variant {s.variant} cutoff {s.cutoff} splitk {s.splitk}",
+          flush=True)
+    C = run(g, A, B, n, n, n, None, ldc_pad=0)
+    check_full(A, B, C, n, n, n, f"{n}^3 library")
