@@ -26,6 +26,7 @@ sys.path.insert(0, ROOT)
 
 LDS_PEAK = 256 * 2.4e9 * 256            # bytes/s: 64 banks x 4 B per clock, 256 CUs, 2.4 GHz
 VALU_WORD_XOR_PEAK = 256 * 64 * 2.4e9   # 64-bit table-row additions/s at one v_bitop3 per 2 words per lane
+MFMA_I8_PEAK = 5.0e15                     # int8 dense matrix-core ops/s (one multiply-accumulate = 2 ops)
 BUILD_BYTES = 256 * 64 * 4                # LDS bytes stored per table build: 256 entries x 64 B x 4 tables (= 64 KiB
                                           # for every tile family: t tables x 256 entries x tile width)
 BUILD_XORS = 255 * 32                     # 64-bit XORs per build: 255 entries x (t x tile words = 32)
@@ -37,6 +38,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=32768)
+    ap.add_argument("--kernel", choices=["m4rm", "mfma"], default="m4rm",
+                    help="base case of the timed product (mfma: the int8 matrix-core parity kernel)")
     ap.add_argument("--variant", type=int, default=None)
     ap.add_argument("--cutoff", type=int, default=None)
     ap.add_argument("--no-cpu", action="store_true")
@@ -461,6 +464,8 @@ def main():
         return
     n = args.n
     sched = default_schedule(g, n)
+    if args.kernel == "mfma":
+        sched = g.Schedule(g.KERNEL_MFMA, 0, 0, 1)
     if args.variant is not None:
         sched.variant = args.variant
     if args.cutoff is not None:
@@ -485,16 +490,33 @@ def main():
 
     C = dC.cpu().numpy().view(np.uint64)    # the timed product; the CPU leg compares rows of it
 
-    m4 = [r for r in recs if r[0] == "m4rm"]
-    launches = len(m4)
-    work = sum(r[2] for r in m4) / max(1, launches)
-    kms = sum(r[3] for r in m4) / max(1, launches)
-    # Algorithmic LDS bytes of a leaf launch: 8 B of table read per 64-bit table-row addition,
-    # plus 64 KiB of table stored per build (one build per barrier phase per tile).
-    builds = table_builds(n, sched)
-    builds = builds * args.steps / max(1, launches) if builds is not None else 0.0
-    lookup_bytes, build_bytes = 8.0 * work, BUILD_BYTES * builds
-    achieved = (lookup_bytes + build_bytes) / (kms * 1e-3)
+    if args.kernel == "mfma":
+        mf = [r for r in recs if r[0] == "mfma"]
+        launches = len(mf)
+        work = sum(r[2] for r in mf) / max(1, launches)      # multiply-accumulates per launch
+        kms = sum(r[3] for r in mf) / max(1, launches)
+        roofline = {"bound": "mfma", "kernel": "int8 matrix-core base", "achieved": 2.0 * work / (kms * 1e-3) / 1e12,
+                    "peak": MFMA_I8_PEAK / 1e12, "unit": "TOP/s", "frac": 2.0 * work / (kms * 1e-3) / MFMA_I8_PEAK,
+                    "traffic": None, "launches_per_step": launches / max(1, args.steps), "kernel_ms": kms,
+                    "macs_per_launch": work}
+    else:
+        m4 = [r for r in recs if r[0] == "m4rm"]
+        launches = len(m4)
+        work = sum(r[2] for r in m4) / max(1, launches)
+        kms = sum(r[3] for r in m4) / max(1, launches)
+        # Algorithmic LDS bytes of a leaf launch: 8 B of table read per 64-bit table-row addition,
+        # plus 64 KiB of table stored per build (one build per barrier phase per tile).
+        builds = table_builds(n, sched)
+        builds = builds * args.steps / max(1, launches) if builds is not None else 0.0
+        lookup_bytes, build_bytes = 8.0 * work, BUILD_BYTES * builds
+        achieved = (lookup_bytes + build_bytes) / (kms * 1e-3)
+        roofline = {"bound": "lds", "kernel": "m4rm leaves", "achieved": achieved / 1e9, "peak": LDS_PEAK / 1e9,
+                    "unit": "GB/s", "frac": achieved / LDS_PEAK, "traffic": traffic_from_profile(n, sched),
+                    "launches_per_step": launches / max(1, args.steps), "kernel_ms": kms,
+                    "word_xors_per_launch": work, "table_builds_per_launch": builds,
+                    "lookup_bytes_per_launch": lookup_bytes, "build_bytes_per_launch": build_bytes,
+                    "frac_lookups_only": lookup_bytes / (kms * 1e-3) / LDS_PEAK,
+                    "valu_roof_frac": ((work + BUILD_XORS * builds) / VALU_WORD_XOR_PEAK) / (kms * 1e-3)}
     out = {
         "metric": "ms and effective GF(2) bit-ops/s per n x n product, % roofline",
         "value": 2.0 * n ** 3 / (ms * 1e-3),
@@ -506,19 +528,13 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "u64 (bit-packed GF(2))",
+        "dtype": "u64 (bit-packed GF(2))" if args.kernel == "m4rm" else "i8 (0/1 entries, int32 sums)",
         "data": "synthetic",
         "config": {"workload": f"square GF(2) product n={n}, Bernoulli(1/2) bits, packed 64 per word",
-                   "n": n, "schedule": {"kernel": "m4rm", "variant": sched.variant, "cutoff": sched.cutoff,
+                   "n": n, "schedule": {"kernel": args.kernel, "variant": sched.variant, "cutoff": sched.cutoff,
                                         "splitk": sched.splitk},
                    "ms_min": min(per), "ms_median": float(np.median(per)), "bit_exact_sampled_rows": None},
-        "roofline": {"bound": "lds", "kernel": "m4rm leaves", "achieved": achieved / 1e9, "peak": LDS_PEAK / 1e9,
-                     "unit": "GB/s", "frac": achieved / LDS_PEAK, "traffic": traffic_from_profile(n, sched),
-                     "launches_per_step": launches / max(1, args.steps), "kernel_ms": kms,
-                     "word_xors_per_launch": work, "table_builds_per_launch": builds,
-                     "lookup_bytes_per_launch": lookup_bytes, "build_bytes_per_launch": build_bytes,
-                     "frac_lookups_only": lookup_bytes / (kms * 1e-3) / LDS_PEAK,
-                     "valu_roof_frac": ((work + BUILD_XORS * builds) / VALU_WORD_XOR_PEAK) / (kms * 1e-3)},
+        "roofline": roofline,
     }
     if args.batch:
         del dA, dB, dC
