@@ -994,8 +994,8 @@ __global__ __launch_bounds__(P::NT) void m4rm_group(GroupArgs g) {
   while (i + 1 < g.count && g.tile_start[i + 1] <= t) ++i;
   const MulDesc& d = g.d[i];
   const int local = t - g.tile_start[i];
-  const int tiles_m = (d.m + P::BM - 1) / P::BM;
-  P::run(d, local % tiles_m, local / tiles_m, reinterpret_cast<char*>(tab));
+  const int tiles_n = (int)((words(d.n) + P::TW - 1) / P::TW);
+  P::run(d, local / tiles_n, local % tiles_n, reinterpret_cast<char*>(tab));
 }
 
 // Descriptor list in device memory (batched products).
@@ -1011,8 +1011,8 @@ __global__ __launch_bounds__(P::NT) void m4rm_list(const MulDesc* __restrict__ d
   }
   const MulDesc d = ds[lo];
   const int local = t - tile_start[lo];
-  const int tiles_m = (d.m + P::BM - 1) / P::BM;
-  P::run(d, local % tiles_m, local / tiles_m, reinterpret_cast<char*>(tab));
+  const int tiles_n = (int)((words(d.n) + P::TW - 1) / P::TW);
+  P::run(d, local / tiles_n, local % tiles_n, reinterpret_cast<char*>(tab));
 }
 
 struct Variant {
