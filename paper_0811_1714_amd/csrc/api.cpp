@@ -142,32 +142,33 @@ int compute_units() {
   return c;
 }
 
-// Predicted time (ms) of an M4RM schedule on MI355X, fitted to 2914 timed schedules on 70
+// Predicted time (ms) of an M4RM schedule on MI355X, fitted to 2935 timed schedules on 71
 // shapes: 22 from 1024^3 to 32768^3 and rectangles down to n = 129 (every tile the default
-// chooses from, k split and Strassen-Winograd depth), and 48 products below 2^30
-// bit-operations with m, k, n log-uniform in [64, 4096).  The fit weights each shape's
-// schedules within 15% of its fastest six-fold.  Leave-one-shape-out, the schedule it picks
-// is 1.5% slower than the fastest on the small products and 5.1% on the large ones.
+// chooses from, k split and Strassen-Winograd depth), 65536^3 on the tallest tiles, and 48
+// products below 2^30 bit-operations with m, k, n log-uniform in [64, 4096).  The fit weights
+// each shape's schedules within 15% of its fastest six-fold.  The schedule it picks is 1.4%
+// slower than the fastest on the small products and 3.8% on the large ones (leave-one-shape-
+// out, before the 65536^3 timings were added: 1.4% and 4.0%).
 //   * tiles run in rounds of one per compute unit; a Strassen leaf launch whose last round
 //     is at most half full spreads that round's work over all units (``run_leaves``);
 //   * a tile costs, per tile family (rows of B per barrier phase), a fixed start-up, a
 //     cost per phase (table build, barrier, B loads) and a cost per tile row per phase
 //     (lookups); see ``kFamily``;
-//   * operand traffic (A once per column tile, B once per row tile) at 20 TB/s (mostly
-//     cache hits), Strassen passes ((2mk + 2kn + 2.75mn)/8 bytes per node) at 2.4 TB/s, and
-//     a k split's zeroing at 0.8 TB/s plus its atomic XORs at 1.0 TB/s.
+//   * operand traffic (A once per column tile, B once per row tile) at 49 TB/s (mostly
+//     cache hits), Strassen passes ((2mk + 2kn + 2.75mn)/8 bytes per node) at 2.5 TB/s, and
+//     a k split's zeroing at 0.9 TB/s plus its atomic XORs at 1.0 TB/s.
 struct CostFamily {
   int phase_rows;
   double tile_ms, phase_ms, row_phase_ms;
 };
 constexpr CostFamily kFamily[] = {
-    {16, 1.135e-2, 5.096e-4, 6.589e-7},   // two tables per 16-row phase, 1024 columns
-    {32, 1.354e-2, 5.776e-4, 5.039e-7},   // four tables per 32-row phase, 512 columns
-    {64, 1.093e-2, 6.047e-4, 8.915e-7},   // eight tables per 64-row phase, 256 columns
-    {256, 1.171e-2, 2.349e-3, 1.639e-6},  // 32 tables per 256-row phase, 64 columns
+    {16, 1.169e-2, 5.16e-4, 6.578e-7},    // two tables per 16-row phase, 1024 columns
+    {32, 1.459e-2, 5.43e-4, 5.248e-7},    // four tables per 32-row phase, 512 columns
+    {64, 1.159e-2, 5.741e-4, 9.41e-7},    // eight tables per 64-row phase, 256 columns
+    {256, 1.203e-2, 2.473e-3, 1.527e-6},  // 32 tables per 256-row phase, 64 columns
 };
-constexpr double kAddBytesPerMs = 2.376e9, kOperandBytesPerMs = 1.982e10, kZeroBytesPerMs = 7.99e8,
-                 kAtomicBytesPerMs = 9.62e8;
+constexpr double kAddBytesPerMs = 2.456e9, kOperandBytesPerMs = 4.943e10, kZeroBytesPerMs = 9.091e8,
+                 kAtomicBytesPerMs = 9.728e8;
 
 const CostFamily& cost_family(int64_t phase_rows) {
   for (const CostFamily& f : kFamily)

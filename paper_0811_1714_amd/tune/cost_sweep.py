@@ -49,6 +49,9 @@ def small_shapes(count=48, seed=11):
     return out
 
 
+HUGE_SHAPES = [(65536,) * 3]
+
+
 def candidates(m, k, n, min_slice_words=16):
     """(variant, cutoff, k split) triples the default considers for the shape: cutoffs of
     min(m, k, n) / 2, / 4, / 8 of at least 2048, k split only without recursion and with
@@ -61,6 +64,8 @@ def candidates(m, k, n, min_slice_words=16):
         for v in VARIANTS:
             if m * k * n >= 2 ** 45 and c == 0 and v not in (16, 10):
                 continue                      # no recursion at 32768^3: two tiles suffice
+            if m * k * n >= 2 ** 48 and v not in (16, 17, 10):
+                continue                      # 65536^3: the tallest tiles only
             for sk in ((1,) if c else (1, 2, 4, 8, 16, 32)):
                 if sk > 1 and words(k) // sk < min_slice_words:
                     continue
@@ -72,6 +77,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default="cost_sweep.jsonl")
     ap.add_argument("--small", action="store_true", help="products below 2^30 bit-operations instead")
+    ap.add_argument("--huge", action="store_true", help="the 65536^3 product instead")
     ap.add_argument("--min-slice-words", type=int, default=16)
     args = ap.parse_args()
     import torch
@@ -82,12 +88,12 @@ def main():
     g.lib()
     t0 = time.time()
     with open(args.out, "w") as out:
-        for (m, k, n) in (small_shapes() if args.small else SHAPES):
+        for (m, k, n) in (small_shapes() if args.small else HUGE_SHAPES if args.huge else SHAPES):
             A = torch.from_numpy(synth.uniform(1, synth.TAG_A, m, k).view(np.int64)).cuda()
             B = torch.from_numpy(synth.uniform(1, synth.TAG_B, k, n).view(np.int64)).cuda()
             C = torch.empty((m, words(n)), dtype=torch.int64, device="cuda")
             lib = g.resolve_schedule(m, k, n)
-            reps = 3 if m * k * n > 2 ** 42 else (5 if m * k * n > 2 ** 30 else 9)
+            reps = 2 if m * k * n >= 2 ** 48 else 3 if m * k * n > 2 ** 42 else (5 if m * k * n > 2 ** 30 else 9)
             for cand in [None] + candidates(m, k, n, args.min_slice_words):
                 s = None if cand is None else g.Schedule(g.KERNEL_M4RM, cand[0], cand[1], cand[2])
                 ws = g.workspace_bytes(m, k, n, s)

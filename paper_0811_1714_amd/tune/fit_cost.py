@@ -17,7 +17,7 @@ The fit minimises the log error of the predicted time, weighted six-fold on each
 schedules within 15% of its fastest, so the model is sharpest where the choice is made.
 
     python -m paper_0811_1714_amd.tune.fit_cost paper_0811_1714_amd/tune/cost_sweep_mi355x.jsonl \
-        paper_0811_1714_amd/tune/cost_sweep_small_mi355x.jsonl [--cv]
+        paper_0811_1714_amd/tune/cost_sweep_small_mi355x.jsonl paper_0811_1714_amd/tune/cost_sweep_huge_mi355x.jsonl
 """
 import argparse
 import collections
