@@ -143,7 +143,10 @@ def test_rectangular_ragged_full_size(g, m, k, n, p):
 
 def test_batch_4096_log_uniform(g):
     """4096 products, m, k, n log-uniform in [64, 4096), in one graph-captured persistent launch
-    under every policy the benchmark uses; four sampled rows of each product against the oracle."""
+    under every policy the benchmark uses.  Under the first policy every row of every product is
+    checked with Freivalds' test (64 random vectors, so a dropped or misrouted tile of any product
+    fails) and four sampled rows of each product against the oracle; the other policies must give
+    the same bits."""
     import torch
     count = 4096
     dims = [tuple(int(x) for x in r) for r in synth.log_uniform_dims(3, 4, count, 64, 4096)]
@@ -173,9 +176,15 @@ def test_batch_4096_log_uniform(g):
             torch.cuda.synchronize()
             outs = [from_dev(h[4]) for h in host]
             if first is None:
-                for (m, k, n), (A, B, *_), C in zip(dims, host, outs):
+                for i, ((m, k, n), (A, B, *_), C) in enumerate(zip(dims, host, outs)):
                     rows = np.unique(np.linspace(0, m - 1, 4).astype(np.int64))
                     assert np.array_equal(C[rows], oracle.mul_rows(A, B, m, k, n, rows)), f"product {(m, k, n)}"
+                    X = synth.uniform(9000 + i, TAG_FREIVALDS, n, 64)
+                    CX = oracle.mul(C, X, m, n, 64)
+                    ABX = oracle.mul(A, oracle.mul(B, X, k, n, 64), m, k, 64)
+                    assert np.array_equal(CX, ABX), f"product {i} {(m, k, n)}: Freivalds test failed"
+                    if n % 64:
+                        assert not np.any(C[:, -1] >> np.uint64(n % 64)), f"product {i}: padding bits of C not zero"
                 first = outs
             else:
                 for a, b, d in zip(first, outs, dims):

@@ -53,6 +53,40 @@ def test_synth_padding_is_zero_and_garbage_helper_only_touches_padding():
     assert not np.array_equal(A, G)
 
 
+@pytest.mark.parametrize("cols", [1, 5, 63, 64, 65, 127, 130, 191])
+def test_equal_packed_sees_every_valid_bit_and_nothing_else(cols):
+    """The comparator the GPU checks use: a flip of any valid bit, in any row, makes two packed
+    matrices unequal (both argument orders); a flip of a padding bit or of a stride-gap word
+    leaves them equal; a different row count is unequal.  Bits are set by position through
+    pack(), which is itself pinned against numpy.packbits above."""
+    rng = np.random.default_rng(cols)
+    rows = 4
+    W = (cols + 63) // 64
+    ld = W + 2
+    X = np.zeros((rows, ld), dtype=np.uint64)
+    X[:, :W] = oracle.pack(rand_bits(rng, rows, cols))
+    X[:, W:] = rng.integers(0, 1 << 63, size=(rows, ld - W), dtype=np.uint64)
+    assert oracle.equal_packed(X, X.copy(), cols)
+    for r in range(rows):
+        for j in range(cols):
+            one = np.zeros((1, cols), dtype=np.uint8)
+            one[0, j] = 1
+            Z = X.copy()
+            Z[r, :W] ^= oracle.pack(one)[0]
+            assert not oracle.equal_packed(X, Z, cols), f"flip of valid bit ({r}, {j}) not seen"
+            assert not oracle.equal_packed(Z, X, cols), f"flip of valid bit ({r}, {j}) not seen"
+        for j in range(cols, 64 * W):
+            Z = X.copy()
+            Z[r, j >> 6] ^= np.uint64(1) << np.uint64(j & 63)
+            assert oracle.equal_packed(X, Z, cols), f"padding bit ({r}, {j}) compared"
+        for w in range(W, ld):
+            Z = X.copy()
+            Z[r, w] = ~Z[r, w]
+            assert oracle.equal_packed(X, Z, cols), f"stride-gap word ({r}, {w}) compared"
+    assert not oracle.equal_packed(X, X[:-1], cols)
+    assert not oracle.equal_packed(X[:-1], X, cols)
+
+
 def test_splitmix64_published_first_output():
     # splitmix64 seeded with 0: first output 0xE220A8397B1DCDAF (Vigna's reference generator).
     assert synth.splitmix64(0) == 0xE220A8397B1DCDAF

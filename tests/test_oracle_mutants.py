@@ -40,8 +40,19 @@ C_MUTANTS = {
     "padding mask one bit short": ("(((uint64_t)1 << r) - 1)", "(((uint64_t)1 << (r - 1)) - 1)"),
 }
 
-# Mistakes in the Four Russians steps (Section 3) and Algorithm 4 (Section 4).
+# Mistakes in the packed comparator the GPU checks use, the Four Russians steps (Section 3)
+# and Algorithm 4 (Section 4).
 PY_MUTANTS = {
+    "comparator always equal": ("    return bool(np.array_equal(a, b))", "    return True"),
+    "comparator masks the first word": ("        a[:, W - 1] &= mk\n        b[:, W - 1] &= mk",
+                                        "        a[:, 0] &= mk\n        b[:, 0] &= mk"),
+    "comparator skips the last word": ("    a = X[:, :W].copy()\n    b = Y[:, :W].copy()",
+                                       "    a = X[:, :W - 1].copy()\n    b = Y[:, :W - 1].copy()"),
+    "comparator reads the stride gap": ("    a = X[:, :W].copy()\n    b = Y[:, :W].copy()",
+                                        "    a = X.copy()\n    b = Y.copy()"),
+    "comparator mask one bit short": ("        mk = np.uint64((1 << r) - 1)", "        mk = np.uint64((1 << (r - 1)) - 1)"),
+    "comparator skips the last row": ("    a = X[:, :W].copy()\n    b = Y[:, :W].copy()",
+                                      "    a = X[:-1, :W].copy()\n    b = Y[:-1, :W].copy()"),
     "Gray code without the reflection": ("[[1] + c for c in reversed(code)]", "[[1] + c for c in code]"),
     "table row picked from the wrong end": ("src = r + pos[0]", "src = r + (kbits - 1 - pos[0])"),
     "ReadBits least significant first": ("        v = 2 * v + bit\n", "        v = v + (bit << b)\n"),
