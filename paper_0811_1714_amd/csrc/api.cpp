@@ -48,6 +48,11 @@ struct DeviceState {
   hipEvent_t last = nullptr;   // recorded after the last enqueued use
   hipStream_t last_stream = nullptr;
   bool has_last = false;
+  // A graph captured while using ``base`` keeps its address and may be replayed at any time,
+  // so such a buffer is never freed before gf2_shutdown: growing past it allocates a new
+  // buffer and keeps the old one here.
+  bool captured = false;
+  std::vector<void*> retired;
 };
 DeviceState g_dev[kMaxDevices];
 
@@ -71,26 +76,30 @@ class WorkspaceLease {
     ds_->mu.lock();
     locked_ = true;
     stream_ = s;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    st = hip_check(hipStreamIsCapturing(s, &cs), "hipStreamIsCapturing");
+    if (st != GF2_OK) return st;
+    const bool capturing = cs != hipStreamCaptureStatusNone;
     if (need > ds_->bytes) {
-      hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-      st = hip_check(hipStreamIsCapturing(s, &cs), "hipStreamIsCapturing");
-      if (st != GF2_OK) return st;
-      if (cs != hipStreamCaptureStatusNone)
+      if (capturing)
         return set_error(GF2_ERR_CAPTURE, "needs %zu bytes of workspace under stream capture; call "
                          "gf2_reserve_workspace first", need);
       if (fault_alloc()) return set_error(GF2_ERR_ALLOC, "injected allocation failure (GF2_FAULT_ALLOC)");
       st = hip_check(hipDeviceSynchronize(), "hipDeviceSynchronize");
       if (st != GF2_OK) return st;
-      if (ds_->base) (void)hipFree(ds_->base);
-      ds_->base = nullptr;
-      ds_->bytes = 0;
       const size_t grow = need + need / 4 + (1u << 20);
-      if (hipMalloc(&ds_->base, grow) != hipSuccess) {
-        ds_->base = nullptr;
+      void* fresh = nullptr;
+      if (hipMalloc(&fresh, grow) != hipSuccess)
         return set_error(GF2_ERR_ALLOC, "hipMalloc of %zu bytes of workspace failed", grow);
+      if (ds_->base) {
+        if (ds_->captured) ds_->retired.push_back(ds_->base);
+        else (void)hipFree(ds_->base);
       }
+      ds_->base = fresh;
       ds_->bytes = grow;
+      ds_->captured = false;
     }
+    if (capturing && need > 0) ds_->captured = true;
     if (!ds_->last) {
       st = hip_check(hipEventCreateWithFlags(&ds_->last, hipEventDisableTiming), "hipEventCreate");
       if (st != GF2_OK) return st;
@@ -692,6 +701,8 @@ int tune_bucket(int64_t x) { return (int)std::lround(2.0 * std::log2((double)(x 
 std::mutex g_tune_mu;
 std::map<TuneKey, std::vector<float>> g_tune;
 
+// The autotuner's operands and stream, shared by every tuning call: one call at a time.
+std::recursive_mutex g_tscr_mu;
 struct TuneScratch {
   uint64_t* buf = nullptr;
   size_t words = 0;
@@ -700,6 +711,7 @@ struct TuneScratch {
 } g_tscr;
 
 gf2_status autotune_shape(int64_t m, int64_t k, int64_t n, double density, int reps, std::vector<float>& ms) {
+  std::lock_guard<std::recursive_mutex> tlk(g_tscr_mu);
   const int S = num_candidates();
   ms.assign(S, -1.f);
   if (m <= 0 || k <= 0 || n <= 0 || m > INT32_MAX || k > INT32_MAX || n > INT32_MAX)
@@ -1096,6 +1108,7 @@ constexpr size_t kBatchCacheMax = 8;
 // Per-product time of every candidate inside a batch of R copies of the product.
 gf2_status autotune_batch_shape(int64_t m, int64_t k, int64_t n, double density, int reps, std::vector<float>& ms,
                                 int& copies) {
+  std::lock_guard<std::recursive_mutex> tlk(g_tscr_mu);
   const int S = num_candidates();
   ms.assign(S, -1.f);
   if (m <= 0 || k <= 0 || n <= 0 || m > INT32_MAX || k > INT32_MAX || n > INT32_MAX)
@@ -1384,9 +1397,12 @@ const char* gf2_last_error(void) { return g_err; }
 
 void gf2_shutdown(void) {
   gf2_set_model(nullptr, 0, nullptr);
-  if (g_tscr.buf) (void)hipFree(g_tscr.buf);
-  if (g_tscr.stream) (void)hipStreamDestroy(g_tscr.stream);
-  g_tscr = TuneScratch{};
+  {
+    std::lock_guard<std::recursive_mutex> tlk(g_tscr_mu);
+    if (g_tscr.buf) (void)hipFree(g_tscr.buf);
+    if (g_tscr.stream) (void)hipStreamDestroy(g_tscr.stream);
+    g_tscr = TuneScratch{};
+  }
   {
     std::lock_guard<std::mutex> lk(g_batch_mu);
     if (!g_batch_cache.empty()) (void)hipDeviceSynchronize();
@@ -1394,12 +1410,16 @@ void gf2_shutdown(void) {
   }
   for (auto& d : g_dev) {
     std::lock_guard<std::mutex> g(d.mu);
+    if (d.base || !d.retired.empty()) (void)hipDeviceSynchronize();
     if (d.base) (void)hipFree(d.base);
+    for (void* p : d.retired) (void)hipFree(p);
     if (d.last) (void)hipEventDestroy(d.last);
     d.base = nullptr;
     d.bytes = 0;
     d.last = nullptr;
     d.has_last = false;
+    d.captured = false;
+    d.retired.clear();
   }
 }
 
