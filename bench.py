@@ -7,9 +7,15 @@ largest square workload), computed by the library's schedule for that shape
 
 Prints one JSON line.  ``value`` is effective bit-operations per second,
 2*n^3 / (seconds per product) -- one AND and one XOR per inner-product term.
-``roofline`` reports the dominant kernel (the M4RM leaves), timed live with HIP
-event pairs the library records around each of its launches.  ``cpu_baseline``
-times the CPU oracle on a bounded sample of rows of the same product.
+``roofline`` reports the dominant kernel (the launch of all M4RM leaves), timed
+live with HIP event pairs the library records around each of its launches, as
+64-bit table-row additions (table builds included) against the VALU peak; beside
+it the whole product against its roof (leaves at the VALU peak plus the
+Strassen-Winograd passes at the HBM peak) and the leaf launch's LDS traffic
+against the LDS rates the library's probe kernels measure in the same run.
+``batch`` times 4096 log-uniform products batched (fixed and learned schedules)
+against the plain form.  ``cpu_baseline`` times the CPU oracle, built for this
+host, on bounded samples of rows of the same product at 1 and at all threads.
 """
 from __future__ import annotations
 
@@ -24,8 +30,10 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-LDS_PEAK = 256 * 2.4e9 * 256            # bytes/s: 64 banks x 4 B per clock, 256 CUs, 2.4 GHz
-VALU_WORD_XOR_PEAK = 256 * 64 * 2.4e9   # 64-bit table-row additions/s at one v_bitop3 per 2 words per lane
+VALU_WORD_XOR_PEAK = 256 * 64 * 2.4e9   # 64-bit table-row additions/s: 256 CUs x 64 lanes x 2.4 GHz, one
+                                          # v_bitop3 on a 32-bit half folds two table words into the sum
+HBM_PEAK = 8.0e12                         # bytes/s
+LDS_NOMINAL = 256 * 2.4e9 * 256           # bytes/s: 64 banks x 4 B per clock, 256 CUs, 2.4 GHz (reference only)
 MFMA_I8_PEAK = 5.0e15                     # int8 dense matrix-core ops/s (one multiply-accumulate = 2 ops)
 BUILD_BYTES = 256 * 64 * 4                # LDS bytes stored per table build: 256 entries x 64 B x 4 tables (= 64 KiB
                                           # for every tile family: t tables x 256 entries x tile width)
@@ -48,7 +56,10 @@ def parse():
     ap.add_argument("--sweep-n", type=int, nargs="*", default=None)
     ap.add_argument("--sweep-variants", type=int, nargs="*", default=None)
     ap.add_argument("--copy-calibration", action="store_true", help="run a plain 1 GiB device copy (counter scale)")
-    ap.add_argument("--batch", type=int, default=0, help="also time a batch of this many log-uniform products")
+    ap.add_argument("--lds-calibration", action="store_true",
+                    help="measure LDS read and write bandwidth with the library's probe kernels")
+    ap.add_argument("--batch", type=int, default=4096,
+                    help="also time a batch of this many log-uniform products (0: skip)")
     ap.add_argument("--rect", action="store_true", help="time the rectangular and ragged products (library schedule)")
     ap.add_argument("--ablation", action="store_true",
                     help="base-case variants of Section 3 at equal size: one table per stripe, t = 2, t = 8")
@@ -61,10 +72,15 @@ def parse():
 
 
 def default_schedule(g, n):
-    """Headline schedule, from the MI355X sweep (and the library's own cost model): two
-    Strassen-Winograd levels (cutoff n/4) over the four-table M4RM tile of 2048 rows x 512
-    columns, which covers each 8192-row leaf of the 32768 product in four row tiles."""
-    return g.Schedule(g.KERNEL_M4RM, 16, n // 4 if n >= 8192 else 0, 1)
+    """The schedule the library itself runs for an n x n product under its default policy (the
+    cost model's choice; at n = 32768: two Strassen-Winograd levels over the four-table M4RM
+    tile of 2048 rows x 512 columns)."""
+    pol = g.get_policy()
+    g.set_policy(g.POLICY_FIXED)
+    try:
+        return g.resolve_schedule(n, n, n)
+    finally:
+        g.set_policy(pol)
 
 
 def m4rm_source_hash():
@@ -97,6 +113,35 @@ def copy_calibration():
         dst.copy_(src)
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes": nbytes, "launches": 3}), flush=True)
+
+
+def lds_calibration(g, quiet=False):
+    """LDS bandwidth of the probe kernels (reads as the lookups issue them, writes as the table
+    build issues them), timed with HIP events on the launch stream: the measured ceiling for
+    the M4RM kernels' table traffic."""
+    import torch
+    blocks = 8 * 256
+    out = torch.empty(blocks * 1024, dtype=torch.int64, device="cuda")
+    stream = torch.cuda.current_stream()
+    res = {}
+    for mode, name, iters in ((0, "read_b128", 64), (1, "write_b32", 256)):
+        for _ in range(2):
+            g.lds_probe(mode, blocks, iters, out, stream)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        times = []
+        for _ in range(5):
+            e0.record(stream)
+            nbytes = g.lds_probe(mode, blocks, iters, out, stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        ms = float(np.median(times))
+        res[name] = {"bytes": nbytes, "ms": ms, "bytes_per_s": nbytes / (ms * 1e-3),
+                     "bytes_per_clk_per_cu_at_2.4GHz": nbytes / (ms * 1e-3) / (256 * 2.4e9)}
+    if not quiet:
+        print(json.dumps({"lds_calibration": res}), flush=True)
+    return res
 
 
 def to_dev(a):
@@ -393,26 +438,57 @@ def batch_bench(g, count, steps, warmup, seed=3, lo=64, hi=4096):
     return out
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(A, B, C, n, seconds):
-    """The oracle on a bounded sample of rows of the same product (about ``seconds`` of CPU
-    work, all host threads), timed; the rows it computes are also compared with those rows of
-    the GPU's product ``C`` (host copy).  Returns (baseline record, rows bit-exact)."""
+    """The oracle (row-by-row packed XOR, Sections 1 and 2) on bounded samples of rows of the same
+    product, timed on this host: first at one thread, then at every thread OpenMP is given, each
+    about ``seconds / 2`` of CPU time.  The oracle is compiled here with -O3 -march=native (the
+    in-tree build is generic x86-64).  The rows it computes are compared with those rows of the
+    GPU's product ``C`` (host copy).  Returns (baseline record, rows bit-exact)."""
+    import tempfile
     import oracle
+    from oracle import build as obuild
+    build_dir = tempfile.mkdtemp(prefix="gf2ref_native_")
+    try:
+        oracle.use_library(obuild.build(native=True, out_dir=build_dir))
+        flags = obuild.command(native=True)
+    except Exception as e:                      # no compiler on this host: the in-tree -O3 build
+        oracle.use_library(None)
+        flags = obuild.command(native=False) + f" (native build failed: {type(e).__name__})"
+
+    def timed(threads, budget):
+        rows = 4
+        t0 = time.perf_counter()
+        oracle.mul_rows(A, B, n, n, n, np.arange(rows), nthreads=threads)
+        dt = time.perf_counter() - t0
+        rows = int(max(4, min(n, rows * budget / max(dt, 1e-6))))
+        sel = np.arange(rows) * (n // rows)
+        t0 = time.perf_counter()
+        ref = oracle.mul_rows(A, B, n, n, n, sel, nthreads=threads)
+        dt = time.perf_counter() - t0
+        return rows, dt, bool(np.array_equal(C[sel], ref))
+
     threads = oracle.max_threads()
-    rows = 8
-    t0 = time.perf_counter()
-    oracle.mul_rows(A, B, n, n, n, np.arange(rows), nthreads=threads)
-    dt = time.perf_counter() - t0
-    rows = int(max(8, min(n, rows * seconds / max(dt, 1e-6))))
-    sel = np.arange(rows) * (n // rows)
-    t0 = time.perf_counter()
-    ref = oracle.mul_rows(A, B, n, n, n, sel, nthreads=threads)
-    dt = time.perf_counter() - t0
-    exact = bool(np.array_equal(C[sel], ref))
-    return ({"value": 2.0 * rows * n * n / dt, "unit": "bit-ops/s", "cores": threads, "kind": "oracle",
-             "sample": f"{rows} of {n} rows of the n={n} product (row-by-row packed XOR), {dt:.1f} s; "
-                       f"the same rows of the GPU product compared: {'bit-exact' if exact else 'DIFFERENT'}"},
-            exact)
+    r1, dt1, ok1 = timed(1, seconds / 2)
+    rn, dtn, okn = timed(threads, seconds / 2)
+    oracle.use_library(None)
+    exact = ok1 and okn
+    rec = {"value": 2.0 * rn * n * n / dtn, "unit": "bit-ops/s", "cores": threads, "kind": "oracle",
+           "sample": f"{rn} of {n} rows of the n={n} product at {threads} threads ({dtn:.1f} s) and {r1} rows at "
+                     f"1 thread ({dt1:.1f} s), row-by-row packed XOR; the same rows of the GPU product compared: "
+                     f"{'bit-exact' if exact else 'DIFFERENT'}",
+           "single_thread": {"value": 2.0 * r1 * n * n / dt1, "unit": "bit-ops/s", "cores": 1},
+           "cpu_model": cpu_model(), "build": flags}
+    return rec, exact
 
 
 def table_builds(n, sched):
@@ -439,6 +515,9 @@ def main():
     g.lib()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.lds_calibration:
+        lds_calibration(g)
         return
     if args.odd_sweep:
         odd_sweep(g)
@@ -502,21 +581,38 @@ def main():
     else:
         m4 = [r for r in recs if r[0] == "m4rm"]
         launches = len(m4)
-        work = sum(r[2] for r in m4) / max(1, launches)
+        work = sum(r[2] for r in m4) / max(1, launches)      # 64-bit table-row additions per launch
         kms = sum(r[3] for r in m4) / max(1, launches)
-        # Algorithmic LDS bytes of a leaf launch: 8 B of table read per 64-bit table-row addition,
-        # plus 64 KiB of table stored per build (one build per barrier phase per tile).
+        # One table build per barrier phase per tile: 8160 64-bit XORs and 64 KiB of LDS stores.
         builds = table_builds(n, sched)
         builds = builds * args.steps / max(1, launches) if builds is not None else 0.0
+        xors = work + BUILD_XORS * builds
+        achieved = xors / (kms * 1e-3)
+        # Whole product against its roof: every leaf's word-XORs (builds included) at the VALU
+        # peak plus the bytes the Strassen-Winograd passes and zero fills move at the HBM peak.
+        pass_bytes = sum(r[2] for r in recs if r[0] in ("strassen_pre", "strassen_post", "fill")) / args.steps
+        t_roof = (xors * launches / args.steps) / VALU_WORD_XOR_PEAK + pass_bytes / HBM_PEAK
+        # LDS, the unit that binds in practice: lookups read 8 B per table-row addition, builds
+        # store 64 KiB each; against the read and write rates the probe kernels measure.
+        lds = lds_calibration(g, quiet=True)
+        rd, wr = lds["read_b128"]["bytes_per_s"], lds["write_b32"]["bytes_per_s"]
         lookup_bytes, build_bytes = 8.0 * work, BUILD_BYTES * builds
-        achieved = (lookup_bytes + build_bytes) / (kms * 1e-3)
-        roofline = {"bound": "lds", "kernel": "m4rm leaves", "achieved": achieved / 1e9, "peak": LDS_PEAK / 1e9,
-                    "unit": "GB/s", "frac": achieved / LDS_PEAK, "traffic": traffic_from_profile(n, sched),
+        t_lds = lookup_bytes / rd + build_bytes / wr
+        roofline = {"bound": "alu", "kernel": "m4rm leaves (all Strassen-Winograd leaves in one launch)",
+                    "achieved": achieved / 1e12, "peak": VALU_WORD_XOR_PEAK / 1e12, "unit": "T word-XOR/s",
+                    "frac": achieved / VALU_WORD_XOR_PEAK, "traffic": traffic_from_profile(n, sched),
                     "launches_per_step": launches / max(1, args.steps), "kernel_ms": kms,
                     "word_xors_per_launch": work, "table_builds_per_launch": builds,
-                    "lookup_bytes_per_launch": lookup_bytes, "build_bytes_per_launch": build_bytes,
-                    "frac_lookups_only": lookup_bytes / (kms * 1e-3) / LDS_PEAK,
-                    "valu_roof_frac": ((work + BUILD_XORS * builds) / VALU_WORD_XOR_PEAK) / (kms * 1e-3)}
+                    "build_xors_per_launch": BUILD_XORS * builds,
+                    "product": {"roof_ms": t_roof * 1e3, "frac": t_roof * 1e3 / ms,
+                                "strassen_and_fill_bytes": pass_bytes},
+                    "fixed_reference": {"what": "kappa=8 M4RM without recursion at the VALU peak",
+                                        "roof_ms": n * ((n + 7) // 8) * ((n + 63) // 64) / VALU_WORD_XOR_PEAK * 1e3,
+                                        "frac": n * ((n + 7) // 8) * ((n + 63) // 64) / VALU_WORD_XOR_PEAK * 1e3 / ms},
+                    "lds": {"lookup_bytes_per_launch": lookup_bytes, "build_bytes_per_launch": build_bytes,
+                            "read_peak_measured": rd, "write_peak_measured": wr,
+                            "roof_ms": t_lds * 1e3, "frac": t_lds * 1e3 / kms,
+                            "frac_of_nominal_read_peak": (lookup_bytes + build_bytes) / (kms * 1e-3) / LDS_NOMINAL}}
     out = {
         "metric": "ms and effective GF(2) bit-ops/s per n x n product, % roofline",
         "value": 2.0 * n ** 3 / (ms * 1e-3),

@@ -218,7 +218,12 @@ size_t gf2_workspace_bytes(int64_t m, int64_t k, int64_t n, const gf2_schedule* 
 
 /* Grow the current device's workspace to at least `bytes` now (synchronising
  * the device), so that later calls -- for instance under stream capture --
- * need no allocation. */
+ * need no allocation.  A call made under stream capture records the
+ * workspace's address into the graph; from then on the library never frees
+ * that buffer before gf2_shutdown(): a later, larger eager call allocates a
+ * new buffer and keeps the captured one, so the graph stays valid to replay
+ * (while no other call on the device uses the workspace at the same time).
+ * Replaying such a graph after gf2_shutdown() is invalid. */
 gf2_status gf2_reserve_workspace(size_t bytes);
 
 /* ---- Launch tracing (for measurement; off by default) ----
@@ -246,6 +251,18 @@ gf2_status gf2_trace_enable(int32_t on);
  * copied; synchronises the recorded events.  Records stay until gf2_trace_clear. */
 gf2_status gf2_trace_read(gf2_trace_record* out, int64_t max, int64_t* count);
 void gf2_trace_clear(void);
+
+/* ---- LDS bandwidth probe (measurement only) ----
+ * The ceiling against which the M4RM kernels' table traffic is reported: their lookups
+ * (Section 3, AddRowFromTable) read LDS and their table builds (MakeTable) write it.
+ * Launches `blocks` workgroups of 1024 threads on `stream`; each issues iters x 64
+ * conflict-free LDS accesses per thread in the four-table tile's pattern: mode 0 reads
+ * 16 B per lane (ds_read_b128), mode 1 writes 4 B per lane (ds_write_b32, whole 256 B
+ * table entries as the Gray-code build writes them).  `out` is a device buffer of
+ * blocks x 1024 words (caller-owned) that receives a reduction of what was read, so no
+ * access can be elided.  *bytes (if not NULL) receives the LDS bytes the launch moves.
+ * Time the launch with events on `stream`.  Bad arguments give GF2_ERR_INVALID_ARG. */
+gf2_status gf2_lds_probe(int32_t mode, int32_t blocks, int32_t iters, uint64_t* out, double* bytes, void* stream);
 
 const char* gf2_status_string(gf2_status s);
 /* Text of the last error raised on the calling thread ("" if none). */

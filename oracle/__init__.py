@@ -32,10 +32,21 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB = None
 
 
+def use_library(path: str | None) -> None:
+    """Load the C routines from another build of ``gf2ref.c`` (for instance the ``-march=native``
+    build the benchmark makes on its own host); None returns to the in-tree build."""
+    global _LIB, _PATH
+    _PATH = path
+    _LIB = None
+
+
+_PATH = None
+
+
 def _lib():
     global _LIB
     if _LIB is None:
-        path = os.path.join(_HERE, "liboracle_gf2.so")
+        path = _PATH or os.path.join(_HERE, "liboracle_gf2.so")
         if not os.path.exists(path):
             from . import build as _build
             _build.build()

@@ -113,6 +113,8 @@ def lib():
     L.gf2_mlp_argmin.restype = ctypes.c_int
     L.gf2_set_model.argtypes = [P, I64, P]
     L.gf2_set_model.restype = ctypes.c_int
+    L.gf2_lds_probe.argtypes = [I32, I32, I32, P, ctypes.POINTER(ctypes.c_double), P]
+    L.gf2_lds_probe.restype = ctypes.c_int
     _LIB = L
     return L
 
@@ -389,3 +391,14 @@ def reserve_workspace(nbytes: int):
 
 def shutdown():
     lib().gf2_shutdown()
+
+
+def lds_probe(mode: int, blocks: int, iters: int, out, stream=None) -> float:
+    """Launch the LDS bandwidth probe (mode 0: 16 B reads, 1: 4 B writes) on ``stream``; ``out``
+    is an int64 CUDA tensor of at least blocks * 1024 words.  Returns the LDS bytes moved."""
+    if out.numel() < blocks * 1024:
+        raise ValueError("out must hold blocks * 1024 words")
+    nbytes = ctypes.c_double(0)
+    _check(lib().gf2_lds_probe(mode, blocks, iters, ctypes.c_void_p(out.data_ptr()), ctypes.byref(nbytes),
+                               _stream_handle(stream)))
+    return nbytes.value

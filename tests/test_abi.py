@@ -150,3 +150,52 @@ def test_resolve_schedule_without_gpu():
             assert e.status == 1
         else:
             raise AssertionError(f"{bad} accepted")
+
+
+def test_autotune_cache_failure_paths(tmp_path):
+    """Corrupt, truncated and missing autotune cache files are refused with GF2_ERR_INVALID_ARG and
+    leave the cache as it was; a well-formed file loads, and saving it back gives the same entries."""
+    import paper_0811_1714_amd as g
+    S = g.num_candidates()
+    g.autotune_clear()
+    good = tmp_path / "good.txt"
+    row = " ".join(str(0.5 + c) for c in range(S))
+    good.write_text(f"20 20 20 {row}\n22 18 14 {row}\n")
+    g.autotune_load(str(good))
+    saved = tmp_path / "saved.txt"
+    g.autotune_save(str(saved))
+    lines = sorted(saved.read_text().split("\n"))
+    assert [ln.split()[:3] for ln in lines if ln] == [["20", "20", "20"], ["22", "18", "14"]]
+    assert all(len(ln.split()) == 3 + S for ln in lines if ln)
+    cases = {
+        "truncated": f"20 20 20 {row}\n24 24 24 " + " ".join(["1.0"] * (S - 1)) + "\n",
+        "not numbers": f"20 20 20 {row}\nx y z {row}\n",
+        "garbage value": f"26 26 26 " + " ".join(["1.0"] * (S - 1)) + " nan?\n",
+        "binary": "\x00\x01\x02\xff\xfe",
+    }
+    for name, text in cases.items():
+        bad = tmp_path / f"{name}.txt"
+        bad.write_bytes(text.encode("latin-1"))
+        with pytest.raises(g.GF2Error) as ei:
+            g.autotune_load(str(bad))
+        assert ei.value.status == 1, name
+        after = tmp_path / f"after_{name}.txt"
+        g.autotune_save(str(after))
+        assert sorted(after.read_text().split("\n")) == lines, f"{name}: cache changed by a refused load"
+    with pytest.raises(g.GF2Error) as ei:
+        g.autotune_load(str(tmp_path / "missing.txt"))
+    assert ei.value.status == 1
+    with pytest.raises(g.GF2Error) as ei:
+        g.autotune_save(str(tmp_path / "no_such_dir" / "x.txt"))
+    assert ei.value.status == 1
+    assert g.lib().gf2_autotune_load(None) == 1
+    g.autotune_clear()
+
+
+def test_lds_probe_argument_errors():
+    L = g.lib()
+    d = ctypes.c_double(0)
+    assert L.gf2_lds_probe(2, 1, 1, P(0x10000), ctypes.byref(d), None) == 1
+    assert L.gf2_lds_probe(0, 0, 1, P(0x10000), ctypes.byref(d), None) == 1
+    assert L.gf2_lds_probe(0, 1, 0, P(0x10000), ctypes.byref(d), None) == 1
+    assert L.gf2_lds_probe(1, 1, 1, P(0), ctypes.byref(d), None) == 1
