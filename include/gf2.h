@@ -101,6 +101,24 @@ gf2_status gf2_mul_sched(uint64_t* C, int64_t ldc, const uint64_t* A, int64_t ld
                          int64_t ldb, int64_t m, int64_t k, int64_t n, int32_t accumulate,
                          const gf2_schedule* sched, void* stream);
 
+/* gf2_mul_sched for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  The
+ * workspace (Strassen-Winograd temporaries, the base kernel's scratch) is a
+ * static device array of GF2_NOALLOC_SCRATCH_BYTES that the library holds on
+ * each GPU it runs on until the process ends; the call allocates no device
+ * memory and does not synchronise.  Under GF2_POLICY_AUTOTUNE a shape missing
+ * from the autotune cache takes the library's default schedule (nothing is
+ * timed).  A schedule whose workspace (gf2_workspace_bytes) exceeds the array
+ * gives GF2_ERR_UNSUPPORTED before anything is enqueued; pass a schedule with
+ * fewer Strassen-Winograd levels (cutoff 0 needs none for the M4RM kernel).
+ * Every call on one GPU uses that GPU's one array, so calls whose work overlaps
+ * in time on one GPU (other streams, other threads) race and give wrong results:
+ * order them, for instance on one stream. */
+#define GF2_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+gf2_status gf2_mul_noalloc(uint64_t* C, int64_t ldc, const uint64_t* A, int64_t lda, const uint64_t* B,
+                           int64_t ldb, int64_t m, int64_t k, int64_t n, int32_t accumulate,
+                           const gf2_schedule* sched, void* stream);
+
 /* The fixed list of candidate schedules that the autotuner and the schedule model
  * choose from (the batched executor's per-product choices).  gf2_candidate copies
  * entry `index` into *out. */

@@ -53,7 +53,8 @@ def lib():
     L.gf2_mul.argtypes = mm + [P]
     L.gf2_addmul.argtypes = mm + [P]
     L.gf2_mul_sched.argtypes = mm + [I32, ctypes.POINTER(Schedule), P]
-    for f in (L.gf2_mul, L.gf2_addmul, L.gf2_mul_sched):
+    L.gf2_mul_noalloc.argtypes = mm + [I32, ctypes.POINTER(Schedule), P]
+    for f in (L.gf2_mul, L.gf2_addmul, L.gf2_mul_sched, L.gf2_mul_noalloc):
         f.restype = ctypes.c_int
     L.gf2_resolve_schedule.argtypes = [I64, I64, I64, ctypes.POINTER(Schedule), ctypes.POINTER(Schedule)]
     L.gf2_resolve_schedule.restype = ctypes.c_int
@@ -163,6 +164,16 @@ def mul_ptr(C, ldc, A, lda, B, ldb, m, k, n, *, accumulate=False, schedule=None,
         _check(L.gf2_addmul(C, ldc, A, lda, B, ldb, m, k, n, s))
     else:
         _check(L.gf2_mul_sched(C, ldc, A, lda, B, ldb, m, k, n, int(accumulate), ctypes.byref(schedule), s))
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20   # GF2_NOALLOC_SCRATCH_BYTES
+
+
+def mul_noalloc_ptr(C, ldc, A, lda, B, ldb, m, k, n, *, accumulate=False, schedule=None, stream=None):
+    """gf2_mul_noalloc: as ``mul_ptr`` with an explicit (or library-chosen) schedule, its workspace
+    the library's static device array (no device allocation)."""
+    _check(lib().gf2_mul_noalloc(C, ldc, A, lda, B, ldb, m, k, n, int(accumulate),
+                                 ctypes.byref(schedule) if schedule is not None else None, _stream_handle(stream)))
 
 
 def mul(C, A, B, m, k, n, *, accumulate=False, schedule=None, stream=None):

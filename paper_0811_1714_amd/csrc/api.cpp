@@ -286,14 +286,16 @@ gf2_schedule default_schedule(int64_t m, int64_t k, int64_t n) {
   return s;
 }
 
-gf2_schedule resolve(const gf2_schedule* req, int64_t m, int64_t k, int64_t n, hipStream_t st) {
+// ``may_time`` false: under the autotune policy a shape missing from the cache takes the
+// default schedule instead of being timed (no allocation, no synchronisation).
+gf2_schedule resolve(const gf2_schedule* req, int64_t m, int64_t k, int64_t n, hipStream_t st, bool may_time = true) {
   gf2_schedule s = default_schedule(m, k, n);
   {
     std::lock_guard<std::mutex> g(g_sched_mu);
     if (!req && g_has_override) req = &g_override;
   }
   if (!req) {
-    const int c = choose_candidate(m, k, n, false, st);
+    const int c = choose_candidate(m, k, n, false, st, may_time);
     if (c >= 0) s = candidate(c);
   }
   if (req) {
@@ -625,19 +627,15 @@ size_t workspace_words(int64_t m, int64_t k, int64_t n, const gf2_schedule& s) {
   return pp.total_words();
 }
 
-gf2_status execute(uint64_t* C, int64_t ldc, const uint64_t* A, int64_t lda, const uint64_t* B, int64_t ldb,
-                   int64_t m, int64_t k, int64_t n, bool accumulate, const gf2_schedule& s, hipStream_t st) {
-  ProductPlan sizing;
-  plan_product(sizing, nullptr, C, ldc, A, lda, B, ldb, m, k, n, accumulate, s);
-  const size_t need = sizing.total_words() * 8;
-  WorkspaceLease lease;
+// Launches of one product whose workspace (Strassen temporaries, then the base kernel's
+// scratch; ``workspace_words`` of them) starts at ``ws``.  Enqueues kernels only.
+gf2_status execute_in(uint64_t* C, int64_t ldc, const uint64_t* A, int64_t lda, const uint64_t* B, int64_t ldb,
+                      int64_t m, int64_t k, int64_t n, bool accumulate, const gf2_schedule& s, hipStream_t st,
+                      uint64_t* ws) {
   gf2_status r = GF2_OK;
-  if (need > 0 && (r = lease.acquire(need, st)) != GF2_OK) return r;
-  uint64_t* ws = static_cast<uint64_t*>(lease.ptr());
   ProductPlan pp;
   plan_product(pp, ws, C, ldc, A, lda, B, ldb, m, k, n, accumulate, s);
   uint64_t* scratch = ws ? ws + pp.st.ws_words : nullptr;
-  if (need > 0) lease.used();
   if (!pp.st.leaves.empty()) {
     // Passes of one recursion depth are independent: pre-additions run depth by depth from
     // the root down, post-additions from the deepest level up, each depth in few launches.
@@ -670,6 +668,16 @@ gf2_status execute(uint64_t* C, int64_t ldc, const uint64_t* A, int64_t lda, con
   if (s.splitk > 1 && words(k) > 1 && !accumulate)
     if ((r = fill_zero(OView{C, ldc, m, words(n), tail_of(n)}, st)) != GF2_OK) return r;
   return run_base(s, pp.leaves, scratch, st);
+}
+
+gf2_status execute(uint64_t* C, int64_t ldc, const uint64_t* A, int64_t lda, const uint64_t* B, int64_t ldb,
+                   int64_t m, int64_t k, int64_t n, bool accumulate, const gf2_schedule& s, hipStream_t st) {
+  const size_t need = workspace_words(m, k, n, s) * 8;
+  WorkspaceLease lease;
+  gf2_status r = GF2_OK;
+  if (need > 0 && (r = lease.acquire(need, st)) != GF2_OK) return r;
+  if (need > 0) lease.used();
+  return execute_in(C, ldc, A, lda, B, ldb, m, k, n, accumulate, s, st, static_cast<uint64_t*>(lease.ptr()));
 }
 
 int num_candidates_fwd() { return num_candidates(); }
@@ -790,7 +798,7 @@ int argmin_allowed(const std::vector<float>& v, bool batch) {
 
 void bump_policy_epoch() { ++g_policy_epoch; }
 
-int choose_candidate(int64_t m, int64_t k, int64_t n, bool batch, hipStream_t s) {
+int choose_candidate(int64_t m, int64_t k, int64_t n, bool batch, hipStream_t s, bool may_time) {
   const int policy = g_policy.load();
   if (policy == GF2_POLICY_MODEL) {
     const int S = num_candidates();
@@ -809,7 +817,7 @@ int choose_candidate(int64_t m, int64_t k, int64_t n, bool batch, hipStream_t s)
       auto it = g_tune.find(TuneKey{tune_bucket(m), tune_bucket(k), tune_bucket(n)});
       if (it != g_tune.end()) ms = it->second;
     }
-    if (ms.empty()) {
+    if (ms.empty() && may_time) {
       hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
       if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone)
         autotune_shape(m, k, n, 0.5, 3, ms);
@@ -818,6 +826,28 @@ int choose_candidate(int64_t m, int64_t k, int64_t n, bool batch, hipStream_t s)
     if (best >= 0) return best;
   }
   return batch ? fixed_candidate(m, k, n) : -1;
+}
+
+gf2_status mul_in_static(uint64_t* C, int64_t ldc, const uint64_t* A, int64_t lda, const uint64_t* B, int64_t ldb,
+                         int64_t m, int64_t k, int64_t n, bool accumulate, const gf2_schedule* sched, void* stream,
+                         size_t max_bytes, ScratchFn scratch) {
+  g_err[0] = 0;
+  gf2_status r = validate(C, ldc, A, lda, B, ldb, m, k, n);
+  if (r != GF2_OK) return r;
+  if ((r = validate_sched(sched)) != GF2_OK) return r;
+  uint64_t* ws = nullptr;
+  if ((r = scratch(&ws)) != GF2_OK) return r;
+  if (m == 0 || n == 0) return GF2_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (k == 0) return accumulate ? GF2_OK : fill_zero(OView{C, ldc, m, words(n), tail_of(n)}, st);
+  const gf2_schedule s = resolve(sched, m, k, n, st, false);
+  const size_t need = workspace_words(m, k, n, s) * 8;
+  if (need > max_bytes)
+    return set_error(GF2_ERR_UNSUPPORTED,
+                     "%lld x %lld x %lld under schedule (kernel %d, variant %d, cutoff %d, splitk %d) needs %zu bytes "
+                     "of workspace; the static scratch holds %zu (choose a schedule with less recursion)",
+                     (long long)m, (long long)k, (long long)n, s.kernel, s.variant, s.cutoff, s.splitk, need, max_bytes);
+  return execute_in(C, ldc, A, lda, B, ldb, m, k, n, accumulate, s, st, need > 0 ? ws : nullptr);
 }
 
 namespace {

@@ -53,7 +53,8 @@ const gf2_schedule& candidate(int i);
 // Candidate index for a product when the caller leaves the choice to the library,
 // under the current policy (fixed heuristic, autotune cache, or schedule model).
 // ``batch`` restricts the choice to schedules the persistent kernel can run.
-int choose_candidate(int64_t m, int64_t k, int64_t n, bool batch, hipStream_t s);
+// ``may_time`` false: no autotune timing (a shape missing from the cache falls back).
+int choose_candidate(int64_t m, int64_t k, int64_t n, bool batch, hipStream_t s, bool may_time = true);
 int fixed_candidate(int64_t m, int64_t k, int64_t n);
 // Schedule model inference on the host copy of the weights: predicted log runtimes.
 bool model_predict(int64_t m, int64_t k, int64_t n, double density, float* out);
@@ -61,6 +62,16 @@ bool model_available();
 gf2_status model_choose_batch(const std::vector<float>& feats_raw, const uint8_t* allowed_host, std::vector<int>& out);
 bool batch_allowed(int candidate);
 void bump_policy_epoch();   // invalidates cached batch plans after a policy or model change
+
+// A product computed in a workspace the caller provides instead of the library's arena:
+// validates, resolves the schedule without autotune timing, and rejects a schedule whose
+// workspace exceeds ``max_bytes`` with GF2_ERR_UNSUPPORTED before anything is enqueued.
+// ``scratch`` returns the workspace's device address for the current device.  Allocates no
+// device memory.
+using ScratchFn = gf2_status (*)(uint64_t** out);
+gf2_status mul_in_static(uint64_t* C, int64_t ldc, const uint64_t* A, int64_t lda, const uint64_t* B, int64_t ldb,
+                         int64_t m, int64_t k, int64_t n, bool accumulate, const gf2_schedule* sched, void* stream,
+                         size_t max_bytes, ScratchFn scratch);
 
 // ---- kernels (each .hip file owns its launches) ----
 // Products launched together with descriptors passed by value in the kernel arguments.
