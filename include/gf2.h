@@ -76,14 +76,19 @@ enum {
 enum { GF2_ODD_PAD = 0, GF2_ODD_PEEL = 1 };
 
 /* A schedule: which base kernel, its tile variant, the Strassen-Winograd
- * crossover, the number of k slices and the odd-size rule.  Zero fields mean
- * "default". */
+ * crossover, the number of k slices, the odd-size rule and the M4RM table
+ * width.  Zero fields mean "default". */
 typedef struct gf2_schedule {
   int32_t kernel;   /* GF2_KERNEL_* */
   int32_t variant;  /* kernel tile variant (see gf2_kernel_variants) */
   int32_t cutoff;   /* recurse while min(m, k, n) > cutoff; 0 = no recursion (Section 5, c_o) */
   int32_t splitk;   /* k split into this many slices XOR-combined into C; 0 or 1 = none */
   int32_t odd;      /* GF2_ODD_PAD or GF2_ODD_PEEL (only with cutoff > 0) */
+  int32_t kappa;    /* M4RM table width k of Section 3.1 (index bits per Gray-code table):
+                     * 0 = 8; 4..7 for the tiles of at most 1024 rows (variants 1-4, 12, 13,
+                     * 18-20; others give GF2_ERR_UNSUPPORTED).  With kappa < 8 each base-case
+                     * product first writes its A's kappa-bit fields out as bytes into the
+                     * workspace; k must stay below kappa * 2^23. */
 } gf2_schedule;
 
 /* C := A*B.  Section 1 / Section 2.3 definition above.  m, k, n >= 0.

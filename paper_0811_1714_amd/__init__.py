@@ -32,11 +32,11 @@ class GF2Error(RuntimeError):
 
 class Schedule(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_int32), ("variant", ctypes.c_int32), ("cutoff", ctypes.c_int32),
-                ("splitk", ctypes.c_int32), ("odd", ctypes.c_int32)]
+                ("splitk", ctypes.c_int32), ("odd", ctypes.c_int32), ("kappa", ctypes.c_int32)]
 
     def __repr__(self):
         return (f"Schedule(kernel={self.kernel}, variant={self.variant}, cutoff={self.cutoff}, "
-                f"splitk={self.splitk}, odd={self.odd})")
+                f"splitk={self.splitk}, odd={self.odd}, kappa={self.kappa})")
 
 
 def lib():

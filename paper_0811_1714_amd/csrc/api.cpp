@@ -135,6 +135,9 @@ gf2_schedule g_override{};
 
 uint64_t tail_of(int64_t cols) { return (cols & 63) ? ((1ull << (cols & 63)) - 1) : ~0ull; }
 
+// M4RM table width of a schedule (0 in a schedule means 8).
+inline int kappa_of(const gf2_schedule& s) { return s.kappa > 0 ? s.kappa : 8; }
+
 
 bool splittable(int64_t m, int64_t k, int64_t n, int64_t cutoff);
 
@@ -304,7 +307,9 @@ gf2_schedule resolve(const gf2_schedule* req, int64_t m, int64_t k, int64_t n, h
     s.cutoff = req->cutoff;
     if (req->splitk > 0) s.splitk = req->splitk;
     s.odd = req->odd;
+    s.kappa = req->kappa;
   }
+  if (s.kappa <= 0) s.kappa = 8;
   return s;
 }
 
@@ -353,6 +358,17 @@ gf2_status validate_sched(const gf2_schedule* s) {
   if (s->cutoff < 0) return set_error(GF2_ERR_INVALID_ARG, "negative cutoff");
   if (s->splitk < 0 || s->splitk > kMaxGroup) return set_error(GF2_ERR_INVALID_ARG, "splitk must be in [0, %d]", kMaxGroup);
   if (s->odd != GF2_ODD_PAD && s->odd != GF2_ODD_PEEL) return set_error(GF2_ERR_INVALID_ARG, "unknown odd-size rule %d", s->odd);
+  if (s->kappa != 0 && (s->kappa < 4 || s->kappa > 8))
+    return set_error(GF2_ERR_INVALID_ARG, "table width %d outside 4..8", s->kappa);
+  if (s->kernel == GF2_KERNEL_M4RM && s->kappa != 0 && !m4rm_has_kappa(s->variant, s->kappa))
+    return set_error(GF2_ERR_UNSUPPORTED, "M4RM variant %d has no %d-bit tables", s->variant, s->kappa);
+  return GF2_OK;
+}
+
+// A resolved schedule the kernels can run (the M4RM tile offers its table width).
+gf2_status check_resolved(const gf2_schedule& s) {
+  if (s.kernel == GF2_KERNEL_M4RM && !m4rm_has_kappa(s.variant, kappa_of(s)))
+    return set_error(GF2_ERR_UNSUPPORTED, "M4RM variant %d has no %d-bit tables", s.variant, kappa_of(s));
   return GF2_OK;
 }
 
@@ -397,7 +413,7 @@ gf2_status run_base(const gf2_schedule& s, const std::vector<MulDesc>& ds, uint6
       return GF2_OK;
     case GF2_KERNEL_M4RM:
     default:
-      return m4rm_launch_group(ds.data(), (int)ds.size(), s.variant, st);
+      return m4rm_launch_group(ds.data(), (int)ds.size(), s.variant, st, 0, kappa_of(s));
   }
 }
 
@@ -534,7 +550,8 @@ void plan_splitk(std::vector<MulDesc>& out, const View& A, const View& B, uint64
 // result has its region zeroed first.
 gf2_status run_fixups(const gf2_schedule& s, const std::vector<MulDesc>& ds, uint64_t* scratch, hipStream_t st) {
   if (ds.empty()) return GF2_OK;
-  if (s.kernel != GF2_KERNEL_M4RM) return run_base(s, ds, scratch, st);
+  // Narrow tables read A's index expansion, which a k slice cannot take apart: launch as planned.
+  if (s.kernel != GF2_KERNEL_M4RM || kappa_of(s) < 8) return run_base(s, ds, scratch, st);
   gf2_status r;
   std::map<int, std::vector<MulDesc>> by_variant;
   for (const MulDesc& d : ds) {
@@ -563,7 +580,7 @@ gf2_status run_fixups(const gf2_schedule& s, const std::vector<MulDesc>& ds, uin
 // one more full round.  Example: 32768^3 at two levels, 1408-row tiles: 2352 tiles are
 // 9.19 rounds on 256 units; one leaf of 48 tiles becomes 5 x 48 slices of a fifth each.
 gf2_status run_leaves(const gf2_schedule& s, const std::vector<MulDesc>& leaves, uint64_t* scratch, hipStream_t st) {
-  if (s.kernel != GF2_KERNEL_M4RM || leaves.size() < 2 || leaves.size() > (size_t)kMaxGroup)
+  if (s.kernel != GF2_KERNEL_M4RM || kappa_of(s) < 8 || leaves.size() < 2 || leaves.size() > (size_t)kMaxGroup)
     return run_base(s, leaves, scratch, st);
   const int64_t cus = compute_units();
   std::vector<int64_t> t(leaves.size());
@@ -599,26 +616,49 @@ gf2_status run_leaves(const gf2_schedule& s, const std::vector<MulDesc>& leaves,
 struct ProductPlan {
   StrassenPlan st;
   std::vector<MulDesc> leaves;   // when not recursing
-  size_t scratch_words = 0;
-  size_t total_words() const { return st.ws_words + scratch_words; }
+  std::vector<ExpandOp> expands; // table width < 8: each base product's A as index bytes
+  size_t x_words = 0;            // their workspace, after the Strassen temporaries
+  size_t scratch_words = 0;      // the base kernel's scratch, after the expansions
+  size_t total_words() const { return st.ws_words + x_words + scratch_words; }
 };
+
+// Table width < 8: every base product reads an index expansion of its A (m4rm_expand) placed
+// in the workspace at ``xbase`` (nullptr: sizing only) and is pointed at it.  Expansions run
+// after the Strassen pre-additions, which write some of these A's.
+void plan_expansions(ProductPlan& pp, uint64_t* xbase, int kappa, const std::vector<MulDesc*>& ds) {
+  for (MulDesc* d : ds) {
+    const int64_t ldx = m4rm_expanded_ld(d->k, kappa);
+    uint64_t* X = xbase ? xbase + pp.x_words : nullptr;
+    pp.x_words += align_words((size_t)((int64_t)d->m * ldx));
+    if (xbase) {
+      pp.expands.push_back(ExpandOp{d->A, X, d->lda, ldx, d->m, d->k, kappa, 0});
+      d->A = X;
+      d->lda = ldx;
+    }
+  }
+}
 
 void plan_product(ProductPlan& pp, uint64_t* base, uint64_t* C, int64_t ldc, const uint64_t* A, int64_t lda,
                   const uint64_t* B, int64_t ldb, int64_t m, int64_t k, int64_t n, bool accumulate,
                   const gf2_schedule& s) {
   const int out = accumulate ? OUT_XOR : OUT_STORE;
   const View Av{A, lda, m, k}, Bv{B, ldb, k, n};
+  const bool narrow = s.kernel == GF2_KERNEL_M4RM && kappa_of(s) < 8;
+  std::vector<MulDesc*> base_ds;
   if (splittable(m, k, n, s.cutoff)) {
     plan_node(pp.st, base, Av, Bv, C, ldc, out, s.cutoff, s.odd);
-    std::vector<MulDesc> all = pp.st.leaves;
-    for (const auto& f : pp.st.kfix) all.push_back(f.second);
-    all.insert(all.end(), pp.st.fix.begin(), pp.st.fix.end());
-    pp.scratch_words = base_scratch_words(s, all);
+    for (MulDesc& d : pp.st.leaves) base_ds.push_back(&d);
+    for (auto& f : pp.st.kfix) base_ds.push_back(&f.second);
+    for (MulDesc& d : pp.st.fix) base_ds.push_back(&d);
   } else {
     if (s.splitk > 1 && words(k) > 1) plan_splitk(pp.leaves, Av, Bv, C, ldc, s.splitk);
     else pp.leaves.push_back(make_desc(Av, Bv, C, ldc, out));
-    pp.scratch_words = base_scratch_words(s, pp.leaves);
+    for (MulDesc& d : pp.leaves) base_ds.push_back(&d);
   }
+  if (narrow) plan_expansions(pp, base ? base + pp.st.ws_words : nullptr, kappa_of(s), base_ds);
+  std::vector<MulDesc> all;
+  for (const MulDesc* d : base_ds) all.push_back(*d);
+  pp.scratch_words = base_scratch_words(s, all);
 }
 
 size_t workspace_words(int64_t m, int64_t k, int64_t n, const gf2_schedule& s) {
@@ -635,7 +675,7 @@ gf2_status execute_in(uint64_t* C, int64_t ldc, const uint64_t* A, int64_t lda, 
   gf2_status r = GF2_OK;
   ProductPlan pp;
   plan_product(pp, ws, C, ldc, A, lda, B, ldb, m, k, n, accumulate, s);
-  uint64_t* scratch = ws ? ws + pp.st.ws_words : nullptr;
+  uint64_t* scratch = ws ? ws + pp.st.ws_words + pp.x_words : nullptr;
   if (!pp.st.leaves.empty()) {
     // Passes of one recursion depth are independent: pre-additions run depth by depth from
     // the root down, post-additions from the deepest level up, each depth in few launches.
@@ -648,6 +688,7 @@ gf2_status execute_in(uint64_t* C, int64_t ldc, const uint64_t* A, int64_t lda, 
       if ((r = strassen_pre_ops(pre.data() + i, (int)(j - i), st)) != GF2_OK) return r;
       i = j;
     }
+    if ((r = m4rm_expand(pp.expands.data(), (int)pp.expands.size(), st)) != GF2_OK) return r;
     if ((r = run_leaves(s, pp.st.leaves, scratch, st)) != GF2_OK) return r;
     if ((r = run_fixups(s, pp.st.fix, scratch, st)) != GF2_OK) return r;
     int maxd = 0;
@@ -667,6 +708,7 @@ gf2_status execute_in(uint64_t* C, int64_t ldc, const uint64_t* A, int64_t lda, 
   }
   if (s.splitk > 1 && words(k) > 1 && !accumulate)
     if ((r = fill_zero(OView{C, ldc, m, words(n), tail_of(n)}, st)) != GF2_OK) return r;
+  if ((r = m4rm_expand(pp.expands.data(), (int)pp.expands.size(), st)) != GF2_OK) return r;
   return run_base(s, pp.leaves, scratch, st);
 }
 
@@ -693,6 +735,7 @@ gf2_status mul_impl(uint64_t* C, int64_t ldc, const uint64_t* A, int64_t lda, co
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (k == 0) return accumulate ? GF2_OK : fill_zero(OView{C, ldc, m, words(n), tail_of(n)}, st);
   const gf2_schedule s = resolve(sched, m, k, n, st);
+  if ((r = check_resolved(s)) != GF2_OK) return r;
   return execute(C, ldc, A, lda, B, ldb, m, k, n, accumulate, s, st);
 }
 
@@ -841,6 +884,7 @@ gf2_status mul_in_static(uint64_t* C, int64_t ldc, const uint64_t* A, int64_t ld
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (k == 0) return accumulate ? GF2_OK : fill_zero(OView{C, ldc, m, words(n), tail_of(n)}, st);
   const gf2_schedule s = resolve(sched, m, k, n, st, false);
+  if ((r = check_resolved(s)) != GF2_OK) return r;
   const size_t need = workspace_words(m, k, n, s) * 8;
   if (need > max_bytes)
     return set_error(GF2_ERR_UNSUPPORTED,
@@ -869,6 +913,9 @@ struct BatchPlanImpl {
   std::vector<OView> fills;
   std::vector<PreOp> pre;
   std::vector<PostOp> post;
+  std::vector<ExpandOp> expands;     // index expansions of A (table width < 8), after the pre passes
+  ExpandOp* d_expands = nullptr;
+  int64_t expand_rows = 0;
   // Device copies, pre ops sorted by depth (parents first), post ops deepest first;
   // each group is one multi-op launch.
   OView* d_fills = nullptr;
@@ -896,6 +943,7 @@ struct BatchPlanImpl {
     if (d_fills) (void)hipFree(d_fills);
     if (d_pre) (void)hipFree(d_pre);
     if (d_post) (void)hipFree(d_post);
+    if (d_expands) (void)hipFree(d_expands);
   }
 
   gf2_status enqueue(hipStream_t s) const {
@@ -905,6 +953,8 @@ struct BatchPlanImpl {
         return r;
     for (const Group& gr : pre_groups)
       if ((r = strassen_pre_multi(d_pre + gr.begin, gr.count, gr.max_elems, s)) != GF2_OK) return r;
+    if (!expands.empty() && (r = m4rm_expand_list(d_expands, (int)expands.size(), expand_rows, s)) != GF2_OK)
+      return r;
     {
       TraceScope tr(GF2_TRACE_BATCH, n_items, work, s);
       if ((r = m4rm_launch_persistent(d_descs, d_items, n_items, d_counter, grid, s)) != GF2_OK) return r;
@@ -959,10 +1009,11 @@ gf2_status validate_batch(const gf2_problem* probs, int64_t count) {
   return GF2_OK;
 }
 
-double tile_cost(const MulDesc& d, int variant, int tm) {
-  const int64_t bm = m4rm_tile_rows(variant);
+// Relative run time of one tile, for the queue order: phases x (rows + the table build).
+double tile_cost(const MulDesc& d, int variant, int kappa, int tm) {
+  const int64_t bm = m4rm_tile_rows(variant), pr = m4rm_phase_rows(variant, kappa);
   const int64_t rows = std::min<int64_t>(bm, d.m - (int64_t)tm * bm);
-  return (double)((d.k + 15) / 16) * (double)(rows + 256);
+  return (double)((d.k + pr - 1) / pr) * (double)(rows * (pr / kappa) / 2 + (1 << kappa));
 }
 
 gf2_status build_batch_plan(const gf2_problem* probs, int64_t count, BatchPlanImpl& P) {
@@ -998,7 +1049,7 @@ gf2_status build_batch_plan(const gf2_problem* probs, int64_t count, BatchPlanIm
       ProductPlan pp;
       plan_product(pp, nullptr, p.C, p.ldc, p.A, p.lda, p.B, p.ldb, p.m, p.k, p.n, p.accumulate != 0,
                    candidate_fwd(P.sched[i]));
-      w = pp.st.ws_words;
+      w = pp.st.ws_words + pp.x_words;
       // Products on the int8 matrix core share one grouped launch, so their transposed Bs
       // coexist (sum); other base cases reuse the scratch one product at a time (max).
       if (candidate_fwd(P.sched[i]).kernel == GF2_KERNEL_MFMA) mfma_scratch += pp.scratch_words;
@@ -1021,23 +1072,24 @@ gf2_status build_batch_plan(const gf2_problem* probs, int64_t count, BatchPlanIm
   std::vector<BatchItem> items;
   std::vector<double> cost;
   auto route = [&](const gf2_schedule& s, const std::vector<MulDesc>& leaves) {
+    const int kappa = kappa_of(s);
     if (s.kernel == GF2_KERNEL_M4RM && m4rm_batchable(s.variant)) {
       for (const MulDesc& d : leaves) {
         const int di = (int)descs.size();
         descs.push_back(d);
         const int64_t bm = m4rm_tile_rows(s.variant), tw = m4rm_tile_words(s.variant);
         const int64_t tms = (d.m + bm - 1) / bm, tns = (words(d.n) + tw - 1) / tw;
-        P.work += (double)d.m * ((d.k + 7) / 8) * (double)words(d.n);
+        P.work += (double)d.m * ((d.k + kappa - 1) / kappa) * (double)words(d.n);
         for (int64_t tm = 0; tm < tms; ++tm)
           for (int64_t tn = 0; tn < tns; ++tn) {
-            items.push_back(BatchItem{di, (int32_t)tm, (int32_t)tn, s.variant});
-            cost.push_back(tile_cost(d, s.variant, (int)tm));
+            items.push_back(BatchItem{di, (int32_t)tm, (int32_t)tn, s.variant | (kappa << 8)});
+            cost.push_back(tile_cost(d, s.variant, kappa, (int)tm));
           }
       }
       return;
     }
     for (auto& sd : P.sides)
-      if (sd.s.kernel == s.kernel && sd.s.variant == s.variant) {
+      if (sd.s.kernel == s.kernel && sd.s.variant == s.variant && kappa_of(sd.s) == kappa) {
         sd.ds.insert(sd.ds.end(), leaves.begin(), leaves.end());
         return;
       }
@@ -1056,6 +1108,7 @@ gf2_status build_batch_plan(const gf2_problem* probs, int64_t count, BatchPlanIm
                  p.accumulate != 0, s);
     if (!pp.st.kfix.empty() || !pp.st.fix.empty())
       return set_error(GF2_ERR_UNSUPPORTED, "peeling is not supported in batches");
+    P.expands.insert(P.expands.end(), pp.expands.begin(), pp.expands.end());
     if (!pp.st.leaves.empty()) {
       P.pre.insert(P.pre.end(), pp.st.pre.begin(), pp.st.pre.end());
       P.post.insert(P.post.end(), pp.st.post.begin(), pp.st.post.end());
@@ -1107,6 +1160,8 @@ gf2_status build_batch_plan(const gf2_problem* probs, int64_t count, BatchPlanIm
   if ((r = upload((void**)&P.d_fills, P.fills.data(), P.fills.size() * sizeof(OView))) != GF2_OK) return r;
   if ((r = upload((void**)&P.d_pre, P.pre.data(), P.pre.size() * sizeof(PreOp))) != GF2_OK) return r;
   if ((r = upload((void**)&P.d_post, P.post.data(), P.post.size() * sizeof(PostOp))) != GF2_OK) return r;
+  for (const ExpandOp& o : P.expands) P.expand_rows = std::max<int64_t>(P.expand_rows, o.m);
+  if ((r = upload((void**)&P.d_expands, P.expands.data(), P.expands.size() * sizeof(ExpandOp))) != GF2_OK) return r;
   return GF2_OK;
 }
 

@@ -83,18 +83,33 @@ struct GroupArgs {
   int remap_n;   // workgroups [0, remap_n) use the XCD remap; later ones (a short tail) map 1:1
 };
 
-// M4RM base case (m4rm.hip).
+// M4RM base case (m4rm.hip).  Table width ``kappa`` (index bits per table) is 8 for every
+// tile and 4..7 for the tiles m4rm_has_kappa names; a descriptor launched with kappa < 8 has
+// its A replaced by A's index expansion (m4rm_expand).
 int m4rm_num_variants();
 int m4rm_tile_rows(int variant);
-int m4rm_phase_rows(int variant);   // rows of B consumed per table-build phase (8, 16 or 64)
+int m4rm_phase_rows(int variant, int kappa = 8);   // rows of B consumed per table-build phase
 int m4rm_tile_words(int variant);
+bool m4rm_has_kappa(int variant, int kappa);
 int64_t m4rm_tiles(const MulDesc& d, int variant);
 // The last ``tail`` descriptors (short k slices) are dispatched after all others, outside
 // the XCD remap, so they fill the last round of tiles.
-gf2_status m4rm_launch_group(const MulDesc* descs, int count, int variant, hipStream_t s, int tail = 0);
-gf2_status m4rm_launch_list(const MulDesc* dev_descs, const int* dev_tile_start, int count, int64_t total_tiles,
-                            int variant, hipStream_t s);
-// One queue item of the persistent batch kernel: a C tile of descriptor ``desc``.
+gf2_status m4rm_launch_group(const MulDesc* descs, int count, int variant, hipStream_t s, int tail = 0,
+                             int kappa = 8);
+// Index expansion for tables of kappa < 8 bits: byte j of row r of X = bits kappa*j ..
+// kappa*j + kappa - 1 of row r of A (bits at or past k as zero); X has ldx words per row,
+// ldx = m4rm_expanded_ld(k, kappa), and bytes past ceil(k/kappa) are zero.
+struct ExpandOp {
+  const uint64_t* A;
+  uint64_t* X;
+  int64_t lda, ldx;
+  int32_t m, k, kappa, pad;
+};
+int64_t m4rm_expanded_ld(int64_t k, int kappa);
+gf2_status m4rm_expand(const ExpandOp* ops, int n, hipStream_t s);                          // host array
+gf2_status m4rm_expand_list(const ExpandOp* dev_ops, int n, int64_t max_rows, hipStream_t s);  // device array
+// One queue item of the persistent batch kernel: a C tile of descriptor ``desc``; ``variant``
+// holds the tile variant in bits 0-7 and the table width above.
 struct BatchItem {
   int32_t desc, tm, tn, variant;
 };

@@ -22,6 +22,7 @@
 //    (index in byte 1, lane offset in byte 0, buffer in byte 2); one ds_read_b128
 //    serves four rows per wave instruction (16 lanes x 16 B = one 256 B entry
 //    per row), the pattern that measured fastest on gfx950 LDS.
+#include <algorithm>
 #include <type_traits>
 
 #include "gf2_internal.h"
@@ -59,11 +60,16 @@ __device__ __forceinline__ uint32_t bload1(__amdgpu_buffer_rsrc_t r, int off) {
   return __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
 }
 
+// C is global memory: said explicitly, so that tiles compiled as functions of their own (the
+// persistent kernel's) store with global rather than flat instructions.
+using gword = __attribute__((address_space(1))) uint64_t;
+
 __device__ __forceinline__ void store_word(uint64_t* cp, uint64_t v, int out) {
+  gword* gp = (gword*)cp;
   if (out == OUT_STORE) {
-    *cp = v;
+    *gp = v;
   } else if (out == OUT_XOR) {
-    *cp ^= v;
+    *gp ^= v;
   } else {
     if (v) atomicXor(reinterpret_cast<unsigned long long*>(cp), (unsigned long long)v);
   }
@@ -88,30 +94,41 @@ struct Tile {
 };
 
 // Rows of B for one stripe, one dword per lane: lane j holds columns 32j..32j+31 of
-// the tile for each of the KB rows (rows past k and words past the row read as zero).
+// the tile for each of the KAPPA rows (rows past k and words past the row read as zero).
+template <int KAPPA = KB>
 struct StripeRows {
-  uint32_t r[KB];
+  uint32_t r[KAPPA];
 };
 
-// Byte offsets of a lane's KB rows of B from the start of a phase of ``phase_rows`` rows,
+// log2 of a workgroup's wave count (2, 4, 8 or 16 waves).
+template <int WAVES>
+constexpr int wave_bits() { return WAVES == 16 ? 4 : WAVES == 8 ? 3 : WAVES == 4 ? 2 : 1; }
+
+// Byte offsets of a lane's KAPPA rows of B from the start of a phase of ``phase_rows`` rows,
 // the lane's first row at ``boff``.  A wave needs the rows that select its fixed high index
 // bits (b >= HIB) only where that bit of w is set; the others are pointed one phase further
 // on, past the end of the phase's buffer range, so they load as zero.  The loads then need
 // no branches, which keeps the compiler's count of loads in flight exact (a branch around a
 // load makes it wait for loads it does not need).
-template <int HIB>
-__device__ __forceinline__ void row_offsets(int (&o)[KB], int boff, int ldb_b, int phase_rows, int w) {
+template <int HIB, int KAPPA>
+__device__ __forceinline__ void row_offsets(int (&o)[KAPPA], int boff, int ldb_b, int phase_rows, int w) {
 #pragma unroll
-  for (int b = 0; b < KB; ++b) {
+  for (int b = 0; b < KAPPA; ++b) {
     const bool need = b < HIB || ((w >> (b - HIB)) & 1);
     o[b] = boff + (b + (need ? 0 : phase_rows)) * ldb_b;
   }
 }
 
+// Index bytes per row of A for table width KAPPA: KAPPA = 8 reads A itself (byte j of a
+// row = bits 8j..8j+7); a narrower table reads A's index expansion (byte j = bits
+// KAPPA*j .. KAPPA*j+KAPPA-1, see expand_indices), so every lookup takes one byte either way.
+template <int KAPPA>
+__device__ __forceinline__ int index_bytes(int k) { return (k + KAPPA - 1) / KAPPA; }
+
 template <int WAVES>
-__device__ __forceinline__ void load_stripe(StripeRows& sr, const uint64_t* pb, int64_t ldb, int rows,
+__device__ __forceinline__ void load_stripe(StripeRows<>& sr, const uint64_t* pb, int64_t ldb, int rows,
                                             int64_t row_bytes, int w, int lane) {
-  constexpr int HIB = KB - (WAVES == 16 ? 4 : WAVES == 8 ? 3 : WAVES == 4 ? 2 : 1);  // walked rows
+  constexpr int HIB = KB - wave_bits<WAVES>();  // walked rows
 #pragma unroll
   for (int b = 0; b < KB; ++b) {
     // Rows selecting the wave's fixed high bits are only needed when that bit of w is set;
@@ -123,16 +140,18 @@ __device__ __forceinline__ void load_stripe(StripeRows& sr, const uint64_t* pb, 
 }
 
 // Build this wave's share of one stripe's table into LDS buffer ``buf``: the entries
-// x = (w << HIB) | g(i), i < 2^HIB, g the binary reflected Gray code.  Bit b of x selects
-// B row kp+b, so T[x] = XOR of the selected rows; consecutive Gray codes differ in
-// exactly bit ctz(i), hence each further entry costs one row addition (Section 3.1).
-// One wave instruction writes one whole 256 B entry (lane j = dword j).
-template <int WAVES>
-__device__ __forceinline__ void build_table(char* tab, int buf, int w, int lane, const StripeRows& sr) {
-  constexpr int HIB = KB - (WAVES == 16 ? 4 : WAVES == 8 ? 3 : WAVES == 4 ? 2 : 1);
+// x = (w << HIB) | g(i), i < 2^HIB, g the binary reflected Gray code, HIB = KAPPA minus the
+// wave-count bits.  Bit b of x selects B row kp+b, so T[x] = XOR of the selected rows;
+// consecutive Gray codes differ in exactly bit ctz(i), hence each further entry costs one
+// row addition (Section 3.1).  One wave instruction writes one whole 256 B entry (lane j =
+// dword j); a table of width KAPPA has 2^KAPPA entries.
+template <int WAVES, int KAPPA = KB>
+__device__ __forceinline__ void build_table(char* tab, int buf, int w, int lane, const StripeRows<KAPPA>& sr) {
+  constexpr int HIB = KAPPA - wave_bits<WAVES>();
+  static_assert(HIB >= 0, "every wave must own at least one table entry");
   uint32_t v = 0;
 #pragma unroll
-  for (int b = HIB; b < KB; ++b) v ^= sr.r[b];       // zero where w's bit is clear
+  for (int b = HIB; b < KAPPA; ++b) v ^= sr.r[b];    // zero where w's bit is clear
   char* dst = tab + ((uint32_t)buf << 16) + lane * 4;
   const uint32_t base = (uint32_t)w << HIB;
   *reinterpret_cast<uint32_t*>(dst + base * ENTRY_BYTES) = v;
@@ -182,7 +201,7 @@ __device__ __forceinline__ void m4rm_tile(const MulDesc& d, int tm, int tn, char
 
   // B rows of stripe p+1 are loaded before the lookups of stripe p, so their latency
   // is hidden behind the lookups; the table is built from them afterwards.
-  StripeRows sr;
+  StripeRows<> sr;
   auto fetch = [&](int p) {
     const int64_t kp = (int64_t)p * KB;
     load_stripe<WAVES>(sr, d.B + kp * d.ldb + c0, d.ldb, (int)imin64(d.k - kp, KB), 8 * Wt, w, L);
@@ -276,13 +295,13 @@ __device__ __forceinline__ void m4rm_tile_any(const MulDesc& d, int tm, int tn, 
 // 16 lanes of a lookup instruction cover both halves of the 64 LDS banks (table 0 in
 // banks 0-31, table 1 in banks 32-63) instead of contending for one half.
 constexpr int T2_WORDS = 16;                // 1024 columns per tile
-constexpr int PB = 2 * KB;                  // rows of B per phase
 
-template <int WAVES, int S>
+template <int WAVES, int S, int KAPPA = KB>
 struct Tile2 {
   static constexpr int RW = 8 * S;          // rows per wave: eight per lookup instruction
   static constexpr int BM = WAVES * RW;
-  static constexpr int HIB = KB - (WAVES == 16 ? 4 : WAVES == 8 ? 3 : WAVES == 4 ? 2 : 1);
+  static constexpr int HIB = KAPPA - wave_bits<WAVES>();
+  static constexpr int PR = 2 * KAPPA;      // rows of B per phase
 };
 
 __device__ __forceinline__ uint4 xor3v(uint4 a, uint4 b, uint4 c) {
@@ -290,9 +309,9 @@ __device__ __forceinline__ uint4 xor3v(uint4 a, uint4 b, uint4 c) {
                     __builtin_amdgcn_bitop3_b32(a.z, b.z, c.z, 0x96), __builtin_amdgcn_bitop3_b32(a.w, b.w, c.w, 0x96));
 }
 
-template <int WAVES, int S, int INFL, bool EDGE>
+template <int WAVES, int S, int INFL, int KAPPA, bool EDGE>
 __device__ __forceinline__ void m4rm2_tile(const MulDesc& d, int tm, int tn, char* tab) {
-  using T = Tile2<WAVES, S>;
+  using T = Tile2<WAVES, S, KAPPA>;
   const int tid = threadIdx.x;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int L = tid & 63, g8 = L >> 3, l8 = L & 7;
@@ -302,8 +321,8 @@ __device__ __forceinline__ void m4rm2_tile(const MulDesc& d, int tm, int tn, cha
   const int64_t Wt = Wn - c0;                           // valid words from the tile start
   const int64_t row0 = (int64_t)tm * T::BM + (int64_t)w * T::RW;
   const int rows_here = (int)imin64(d.m - row0, T::RW);
-  const int nphases = (d.k + PB - 1) / PB;
-  const int kdw = (d.k + 31) >> 5;
+  const int nphases = (d.k + T::PR - 1) / T::PR;
+  const int kdw = (index_bytes<KAPPA>(d.k) + 3) >> 2;   // A dwords per row that hold indices
   const int lda_b = (int)(d.lda * 8), ldb_b = (int)(d.ldb * 8);
   // A: dword gd of a row holds the indices of phases 2gd (bytes 0, 1) and 2gd+1 (bytes 2, 3).
   const __amdgpu_buffer_rsrc_t ra =
@@ -320,9 +339,9 @@ __device__ __forceinline__ void m4rm2_tile(const MulDesc& d, int tm, int tn, cha
   // of odd groups in place instead and load one dword per group.
   const uint32_t swp = hsw ? 0x02030001u : 0x03020100u;
   // B: lane L builds column dword L&31 of table L>>5, i.e. rows kp + 8*(L>>5) + b.
-  const int boff = (L >> 5) * KB * ldb_b + (L & 31) * 4;
-  int bo[KB];
-  row_offsets<T::HIB>(bo, boff, ldb_b, PB, w);
+  const int boff = (L >> 5) * KAPPA * ldb_b + (L & 31) * 4;
+  int bo[KAPPA];
+  row_offsets<T::HIB, KAPPA>(bo, boff, ldb_b, T::PR, w);
 
   uint4 acc[S];
 #pragma unroll
@@ -337,13 +356,13 @@ __device__ __forceinline__ void m4rm2_tile(const MulDesc& d, int tm, int tn, cha
 #pragma unroll
     for (int s = 0; s < S; ++s) dst[s] = bload1(ra, (8 * s + g8) * lda_b + 16 * c + 4 * (l8 & 3));
   };
-  StripeRows sr;
+  StripeRows<KAPPA> sr;
   auto fetch = [&](int p) {
-    const int64_t kp = (int64_t)p * PB;
-    const int rows = (int)imin64(d.k - kp, PB);
+    const int64_t kp = (int64_t)p * T::PR;
+    const int rows = (int)imin64(d.k - kp, T::PR);
     const __amdgpu_buffer_rsrc_t rb = make_rsrc(d.B + kp * d.ldb + c0, (int64_t)(rows - 1) * ldb_b + 8 * Wt);
 #pragma unroll
-    for (int b = 0; b < KB; ++b) sr.r[b] = bload1(rb, bo[b]);
+    for (int b = 0; b < KAPPA; ++b) sr.r[b] = bload1(rb, bo[b]);
   };
   constexpr bool kChunked = S <= 8;
   auto load_a = [&](int gd, uint32_t (&dst)[S]) {
@@ -354,7 +373,7 @@ __device__ __forceinline__ void m4rm2_tile(const MulDesc& d, int tm, int tn, cha
     if constexpr (kChunked) load_chunk(0, ax);
     else load_a(0, ax);
     fetch(0);
-    build_table<WAVES>(tab, 0, w, L, sr);
+    build_table<WAVES, KAPPA>(tab, 0, w, L, sr);
   }
   __syncthreads();
 
@@ -379,7 +398,7 @@ __device__ __forceinline__ void m4rm2_tile(const MulDesc& d, int tm, int tn, cha
       for (int s = s0; s < s0 + INFL && s < S; ++s)
         asm volatile("" : "+v"(acc[s].x), "+v"(acc[s].y), "+v"(acc[s].z), "+v"(acc[s].w));
     }
-    if (p + 1 < nphases) build_table<WAVES>(tab, (p & 1) ^ 1, w, L, sr);
+    if (p + 1 < nphases) build_table<WAVES, KAPPA>(tab, (p & 1) ^ 1, w, L, sr);
     __syncthreads();
   };
   // Phase p = 8c + 2jj + U of chunk c (jj, U compile-time).
@@ -469,14 +488,14 @@ __device__ __forceinline__ void m4rm2_tile(const MulDesc& d, int tm, int tn, cha
   }
 }
 
-template <int WAVES, int S, int INFL>
+template <int WAVES, int S, int INFL, int KAPPA>
 __device__ __forceinline__ void m4rm2_tile_any(const MulDesc& d, int tm, int tn, char* tab) {
-  using T = Tile2<WAVES, S>;
+  using T = Tile2<WAVES, S, KAPPA>;
   const int64_t Wn = words(d.n);
   const bool edge = (int64_t)(tm + 1) * T::BM > d.m || (int64_t)(tn + 1) * T2_WORDS > Wn ||
                     ((d.n & 63) != 0 && (int64_t)(tn + 1) * T2_WORDS == Wn);
-  if (edge) m4rm2_tile<WAVES, S, INFL, true>(d, tm, tn, tab);
-  else m4rm2_tile<WAVES, S, INFL, false>(d, tm, tn, tab);
+  if (edge) m4rm2_tile<WAVES, S, INFL, KAPPA, true>(d, tm, tn, tab);
+  else m4rm2_tile<WAVES, S, INFL, KAPPA, false>(d, tm, tn, tab);
 }
 
 // ---------------------------------------------------------------------------
@@ -490,18 +509,18 @@ __device__ __forceinline__ void m4rm2_tile_any(const MulDesc& d, int tm, int tn,
 // qword (its eight indices for the phase) is byte-permuted once so that instruction h
 // finds row r's index for table h ^ (r & 7) in byte h.
 constexpr int T8_WORDS = 4;                 // 256 columns per tile
-constexpr int P8 = 8 * KB;                  // rows of B per phase
 
-template <int WAVES, int S>
+template <int WAVES, int S, int KAPPA = KB>
 struct Tile8 {
   static constexpr int RW = 32 * S;         // rows per wave: 32 per lookup instruction
   static constexpr int BM = WAVES * RW;
-  static constexpr int HIB = KB - (WAVES == 16 ? 4 : WAVES == 8 ? 3 : WAVES == 4 ? 2 : 1);
+  static constexpr int HIB = KAPPA - wave_bits<WAVES>();
+  static constexpr int PR = 8 * KAPPA;      // rows of B per phase
 };
 
-template <int WAVES, int S, bool EDGE>
+template <int WAVES, int S, int KAPPA, bool EDGE>
 __device__ __forceinline__ void m4rm8_tile(const MulDesc& d, int tm, int tn, char* tab) {
-  using T = Tile8<WAVES, S>;
+  using T = Tile8<WAVES, S, KAPPA>;
   const int tid = threadIdx.x;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int L = tid & 63, r32 = L >> 1, half = L & 1;
@@ -511,8 +530,8 @@ __device__ __forceinline__ void m4rm8_tile(const MulDesc& d, int tm, int tn, cha
   const int64_t Wt = Wn - c0;                           // valid words from the tile start
   const int64_t row0 = (int64_t)tm * T::BM + (int64_t)w * T::RW;
   const int rows_here = (int)imin64(d.m - row0, T::RW);
-  const int nphases = (d.k + P8 - 1) / P8;
-  const int kq = (d.k + 63) >> 6;                       // A words per row that hold bits < k
+  const int nphases = (d.k + T::PR - 1) / T::PR;
+  const int kq = (index_bytes<KAPPA>(d.k) + 7) >> 3;    // A words per row that hold indices
   const int lda_b = (int)(d.lda * 8), ldb_b = (int)(d.ldb * 8);
   const __amdgpu_buffer_rsrc_t ra =
       make_rsrc(d.A + row0 * d.lda, rows_here > 0 ? (int64_t)(rows_here - 1) * lda_b + 8 * kq : 0);
@@ -527,9 +546,9 @@ __device__ __forceinline__ void m4rm8_tile(const MulDesc& d, int tm, int tn, cha
     sel_hi |= ((uint32_t)(4 + b) ^ rr) << (8 * b);
   }
   // B: lane L builds column dword L&7 of table L>>3, i.e. rows kp + 8*(L>>3) + b.
-  const int boff = (L >> 3) * KB * ldb_b + (L & 7) * 4;
-  int bo[KB];
-  row_offsets<T::HIB>(bo, boff, ldb_b, P8, w);
+  const int boff = (L >> 3) * KAPPA * ldb_b + (L & 7) * 4;
+  int bo[KAPPA];
+  row_offsets<T::HIB, KAPPA>(bo, boff, ldb_b, T::PR, w);
 
   uint4 acc[S];
 #pragma unroll
@@ -539,18 +558,18 @@ __device__ __forceinline__ void m4rm8_tile(const MulDesc& d, int tm, int tn, cha
 #pragma unroll
     for (int s = 0; s < S; ++s) dst[s] = bload2(ra, (32 * s + r32) * lda_b + 8 * p);
   };
-  StripeRows sr;
+  StripeRows<KAPPA> sr;
   auto fetch = [&](int p) {
-    const int64_t kp = (int64_t)p * P8;
-    const int rows = (int)imin64(d.k - kp, P8);
+    const int64_t kp = (int64_t)p * T::PR;
+    const int rows = (int)imin64(d.k - kp, T::PR);
     const __amdgpu_buffer_rsrc_t rb = make_rsrc(d.B + kp * d.ldb + c0, (int64_t)(rows - 1) * ldb_b + 8 * Wt);
 #pragma unroll
-    for (int b = 0; b < KB; ++b) sr.r[b] = bload1(rb, bo[b]);
+    for (int b = 0; b < KAPPA; ++b) sr.r[b] = bload1(rb, bo[b]);
   };
   if (nphases > 0) {
     load_a(0, ax);
     fetch(0);
-    build_table<WAVES>(tab, 0, w, L, sr);
+    build_table<WAVES, KAPPA>(tab, 0, w, L, sr);
   }
   __syncthreads();
 
@@ -585,7 +604,7 @@ __device__ __forceinline__ void m4rm8_tile(const MulDesc& d, int tm, int tn, cha
         asm volatile("" : "+v"(acc[s].x), "+v"(acc[s].y), "+v"(acc[s].z), "+v"(acc[s].w));
       }
     }
-    if (p + 1 < nphases) build_table<WAVES>(tab, (p & 1) ^ 1, w, L, sr);
+    if (p + 1 < nphases) build_table<WAVES, KAPPA>(tab, (p & 1) ^ 1, w, L, sr);
     __syncthreads();
   };
   int p = 0;
@@ -612,14 +631,14 @@ __device__ __forceinline__ void m4rm8_tile(const MulDesc& d, int tm, int tn, cha
   }
 }
 
-template <int WAVES, int S>
+template <int WAVES, int S, int KAPPA>
 __device__ __forceinline__ void m4rm8_tile_any(const MulDesc& d, int tm, int tn, char* tab) {
-  using T = Tile8<WAVES, S>;
+  using T = Tile8<WAVES, S, KAPPA>;
   const int64_t Wn = words(d.n);
   const bool edge = (int64_t)(tm + 1) * T::BM > d.m || (int64_t)(tn + 1) * T8_WORDS > Wn ||
                     ((d.n & 63) != 0 && (int64_t)(tn + 1) * T8_WORDS == Wn);
-  if (edge) m4rm8_tile<WAVES, S, true>(d, tm, tn, tab);
-  else m4rm8_tile<WAVES, S, false>(d, tm, tn, tab);
+  if (edge) m4rm8_tile<WAVES, S, KAPPA, true>(d, tm, tn, tab);
+  else m4rm8_tile<WAVES, S, KAPPA, false>(d, tm, tn, tab);
 }
 
 // ---------------------------------------------------------------------------
@@ -636,18 +655,18 @@ __device__ __forceinline__ void m4rm8_tile_any(const MulDesc& d, int tm, int tn,
 // four different tables, i.e. all 64 banks.  The address is one v_perm of the row's A dword
 // (its four indices for the phase) with a per-lane selector that picks index byte h ^ (r & 3).
 constexpr int T4_WORDS = 8;                 // 512 columns per tile
-constexpr int P4 = 4 * KB;                  // rows of B per phase
 
-template <int WAVES, int S>
+template <int WAVES, int S, int KAPPA = KB>
 struct Tile4 {
   static constexpr int RW = 16 * S;         // rows per wave: 16 per lookup instruction
   static constexpr int BM = WAVES * RW;
-  static constexpr int HIB = KB - (WAVES == 16 ? 4 : WAVES == 8 ? 3 : WAVES == 4 ? 2 : 1);
+  static constexpr int HIB = KAPPA - wave_bits<WAVES>();
+  static constexpr int PR = 4 * KAPPA;      // rows of B per phase
 };
 
-template <int WAVES, int S, bool EDGE>
+template <int WAVES, int S, int KAPPA, bool EDGE>
 __device__ __forceinline__ void m4rm4_tile(const MulDesc& d, int tm, int tn, char* tab) {
-  using T = Tile4<WAVES, S>;
+  using T = Tile4<WAVES, S, KAPPA>;
   const int tid = threadIdx.x;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int L = tid & 63, r16 = L >> 2, qtr = L & 3;
@@ -657,8 +676,8 @@ __device__ __forceinline__ void m4rm4_tile(const MulDesc& d, int tm, int tn, cha
   const int64_t Wt = Wn - c0;                           // valid words from the tile start
   const int64_t row0 = (int64_t)tm * T::BM + (int64_t)w * T::RW;
   const int rows_here = (int)imin64(d.m - row0, T::RW);
-  const int nphases = (d.k + P4 - 1) / P4;
-  const int kdw = (d.k + 31) >> 5;                      // A dwords per row that hold bits < k
+  const int nphases = (d.k + T::PR - 1) / T::PR;
+  const int kdw = (index_bytes<KAPPA>(d.k) + 3) >> 2;   // A dwords per row that hold indices
   const int lda_b = (int)(d.lda * 8), ldb_b = (int)(d.ldb * 8);
   const __amdgpu_buffer_rsrc_t ra =
       make_rsrc(d.A + row0 * d.lda, rows_here > 0 ? (int64_t)(rows_here - 1) * lda_b + 4 * kdw : 0);
@@ -675,7 +694,7 @@ __device__ __forceinline__ void m4rm4_tile(const MulDesc& d, int tm, int tn, cha
   // the phase's last row (rows at or past k read as zero), and is empty for a row that
   // selects one of the wave's fixed high index bits where that bit of w is clear (such a
   // row is not needed, and must read as zero).  One offset register serves all eight loads.
-  const int boff = (L >> 4) * KB * ldb_b + (L & 15) * 4;
+  const int boff = (L >> 4) * KAPPA * ldb_b + (L & 15) * 4;
 
   uint4 acc[S];
 #pragma unroll
@@ -690,33 +709,33 @@ __device__ __forceinline__ void m4rm4_tile(const MulDesc& d, int tm, int tn, cha
 #pragma unroll
     for (int s = 0; s < S; ++s) dst[s] = bload1(ra, (16 * s + r16) * lda_b + 16 * c + 4 * qtr);
   };
-  StripeRows sr;
+  StripeRows<KAPPA> sr;
   // Ranges fit 31 bits: at most 31 rows of at most 2^24 bytes plus one row's valid bytes.
   const int wt_b = 8 * (int)Wt;
   // Phases are fetched in order, so the row pointer and the rows left advance by one phase
   // per call (no 64-bit multiply per phase).
   const char* bnext = reinterpret_cast<const char*>(d.B + c0);
-  const int64_t bstep = (int64_t)P4 * ldb_b;
+  const int64_t bstep = (int64_t)T::PR * ldb_b;
   int64_t kleft = d.k;
   auto fetch = [&](int) {
-    const int rows = (int)imin64(kleft, P4);              // > -P4 even past the last phase
+    const int rows = (int)imin64(kleft, T::PR);           // > -PR even past the last phase
     const int last = (rows - 1) * ldb_b + wt_b;           // range from the phase's first row
     const char* rowp = bnext;                             // row kp + b, and its range
     int left = last;
 #pragma unroll
-    for (int b = 0; b < KB; ++b) {
+    for (int b = 0; b < KAPPA; ++b) {
       const bool need = b < T::HIB || ((w >> (b - T::HIB)) & 1);
       sr.r[b] = bload1(make_rsrc32(rowp, need ? left : 0), boff);
       rowp += ldb_b;
       left -= ldb_b;
     }
     bnext += bstep;
-    kleft -= P4;
+    kleft -= T::PR;
   };
   if (nphases > 0) {
     load_chunk(0, ax);
     fetch(0);
-    build_table<WAVES>(tab, 0, w, L, sr);
+    build_table<WAVES, KAPPA>(tab, 0, w, L, sr);
   }
   __syncthreads();
 
@@ -745,7 +764,7 @@ __device__ __forceinline__ void m4rm4_tile(const MulDesc& d, int tm, int tn, cha
     // Lookups run at a raised wave priority and the table build at the normal one, so waves
     // still looking up are issued ahead of waves already building (about 1% at 32768^3).
     __builtin_amdgcn_s_setprio(0);
-    if (p + 1 < nphases) build_table<WAVES>(tab, (p & 1) ^ 1, w, L, sr);
+    if (p + 1 < nphases) build_table<WAVES, KAPPA>(tab, (p & 1) ^ 1, w, L, sr);
     __syncthreads();
     __builtin_amdgcn_s_setprio(2);
   };
@@ -797,14 +816,14 @@ __device__ __forceinline__ void m4rm4_tile(const MulDesc& d, int tm, int tn, cha
   }
 }
 
-template <int WAVES, int S>
+template <int WAVES, int S, int KAPPA>
 __device__ __forceinline__ void m4rm4_tile_any(const MulDesc& d, int tm, int tn, char* tab) {
-  using T = Tile4<WAVES, S>;
+  using T = Tile4<WAVES, S, KAPPA>;
   const int64_t Wn = words(d.n);
   const bool edge = (int64_t)(tm + 1) * T::BM > d.m || (int64_t)(tn + 1) * T4_WORDS > Wn ||
                     ((d.n & 63) != 0 && (int64_t)(tn + 1) * T4_WORDS == Wn);
-  if (edge) m4rm4_tile<WAVES, S, true>(d, tm, tn, tab);
-  else m4rm4_tile<WAVES, S, false>(d, tm, tn, tab);
+  if (edge) m4rm4_tile<WAVES, S, KAPPA, true>(d, tm, tn, tab);
+  else m4rm4_tile<WAVES, S, KAPPA, false>(d, tm, tn, tab);
 }
 
 // ---------------------------------------------------------------------------
@@ -953,17 +972,18 @@ __device__ __forceinline__ void m4rm32_tile_any(const MulDesc& d, int tm, int tn
   else m4rm32_tile<WAVES, RPT, false>(d, tm, tn, tab);
 }
 
-// Tile policies: one table per stripe (T1: 2048 columns) or two per phase (T2: 1024).
+// Tile policies: a tile family (tables per phase and tile width), its height and its table
+// width KAPPA (index bits per table, Section 3.1).
 template <int WAVES, int RW>
 struct PolicyT1 {
   static constexpr int BM = WAVES * RW, TW = TILE_WORDS, NT = WAVES * 64, PR = KB;
   __device__ __forceinline__ static void run(const MulDesc& d, int tm, int tn, char* tab) { m4rm_tile_any<WAVES, RW>(d, tm, tn, tab); }
 };
-template <int WAVES, int S, int INFL>
+template <int WAVES, int S, int INFL, int KAPPA = KB>
 struct PolicyT2 {
-  static constexpr int BM = Tile2<WAVES, S>::BM, TW = T2_WORDS, NT = WAVES * 64, PR = PB;
+  static constexpr int BM = Tile2<WAVES, S, KAPPA>::BM, TW = T2_WORDS, NT = WAVES * 64, PR = 2 * KAPPA;
   __device__ __forceinline__ static void run(const MulDesc& d, int tm, int tn, char* tab) {
-    m4rm2_tile_any<WAVES, S, INFL>(d, tm, tn, tab);
+    m4rm2_tile_any<WAVES, S, INFL, KAPPA>(d, tm, tn, tab);
   }
 };
 template <int WAVES, int RPT>
@@ -971,15 +991,15 @@ struct PolicyT32 {
   static constexpr int BM = Tile32<WAVES, RPT>::BM, TW = 1, NT = WAVES * 64, PR = P32;
   __device__ __forceinline__ static void run(const MulDesc& d, int tm, int tn, char* tab) { m4rm32_tile_any<WAVES, RPT>(d, tm, tn, tab); }
 };
-template <int WAVES, int S>
+template <int WAVES, int S, int KAPPA = KB>
 struct PolicyT4 {
-  static constexpr int BM = Tile4<WAVES, S>::BM, TW = T4_WORDS, NT = WAVES * 64, PR = P4;
-  __device__ __forceinline__ static void run(const MulDesc& d, int tm, int tn, char* tab) { m4rm4_tile_any<WAVES, S>(d, tm, tn, tab); }
+  static constexpr int BM = Tile4<WAVES, S, KAPPA>::BM, TW = T4_WORDS, NT = WAVES * 64, PR = 4 * KAPPA;
+  __device__ __forceinline__ static void run(const MulDesc& d, int tm, int tn, char* tab) { m4rm4_tile_any<WAVES, S, KAPPA>(d, tm, tn, tab); }
 };
-template <int WAVES, int S>
+template <int WAVES, int S, int KAPPA = KB>
 struct PolicyT8 {
-  static constexpr int BM = Tile8<WAVES, S>::BM, TW = T8_WORDS, NT = WAVES * 64, PR = P8;
-  __device__ __forceinline__ static void run(const MulDesc& d, int tm, int tn, char* tab) { m4rm8_tile_any<WAVES, S>(d, tm, tn, tab); }
+  static constexpr int BM = Tile8<WAVES, S, KAPPA>::BM, TW = T8_WORDS, NT = WAVES * 64, PR = 8 * KAPPA;
+  __device__ __forceinline__ static void run(const MulDesc& d, int tm, int tn, char* tab) { m4rm8_tile_any<WAVES, S, KAPPA>(d, tm, tn, tab); }
 };
 
 // Up to kMaxGroup products in one launch, descriptors passed by value (no device
@@ -998,36 +1018,31 @@ __global__ __launch_bounds__(P::NT) void m4rm_group(GroupArgs g) {
   P::run(d, local / tiles_n, local % tiles_n, reinterpret_cast<char*>(tab));
 }
 
-// Descriptor list in device memory (batched products).
-template <class P>
-__global__ __launch_bounds__(P::NT) void m4rm_list(const MulDesc* __restrict__ ds, const int* __restrict__ tile_start,
-                                                   int count) {
-  __shared__ uint4 tab[2 * TABLE_BYTES / 16];
-  const int t = xcd_remap(blockIdx.x, gridDim.x);
-  int lo = 0, hi = count - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (tile_start[mid] <= t) lo = mid; else hi = mid - 1;
-  }
-  const MulDesc d = ds[lo];
-  const int local = t - tile_start[lo];
-  const int tiles_n = (int)((words(d.n) + P::TW - 1) / P::TW);
-  P::run(d, local / tiles_n, local % tiles_n, reinterpret_cast<char*>(tab));
-}
+// Table widths: 8 for every tile; the tiles of at most 1024 rows (the ones short enough for
+// the table build to matter, and the persistent kernel's) also 4 to 7.
+constexpr int kKappaMin = 4;
+constexpr int kNumKappa = KB - kKappaMin + 1;
 
 struct Variant {
-  int threads, bm, tw, pr;  // workgroup size, tile rows, tile width in words, B rows per barrier phase
-  void (*group)(GroupArgs);
-  void (*list)(const MulDesc*, const int*, int);
+  int threads, bm, tw, pr;                // workgroup size, tile rows, tile width in words, B rows per phase at 8
+  void (*group[kNumKappa])(GroupArgs);    // by table width - kKappaMin; null where the tile lacks it
 };
 
-// Variants 1..4 (the two-table tiles of 1024 down to 128 rows) can run inside the
-// persistent batch kernel; with only these the kernel fits 128 VGPRs without spills.
+template <class P>
+Variant variant8() {
+  return {P::NT, P::BM, P::TW, P::PR, {nullptr, nullptr, nullptr, nullptr, m4rm_group<P>}};
+}
+template <template <int> class F>
+Variant variantk() {
+  return {F<KB>::NT, F<KB>::BM, F<KB>::TW, F<KB>::PR,
+          {m4rm_group<F<4>>, m4rm_group<F<5>>, m4rm_group<F<6>>, m4rm_group<F<7>>, m4rm_group<F<8>>}};
+}
+
 using V0 = PolicyT2<16, 12, 2>;   // t=2, BM 1536 x 1024 columns
-using V1 = PolicyT2<16, 8, 2>;    // t=2, BM 1024
-using V2 = PolicyT2<16, 4, 4>;    // t=2, BM 512
-using V3 = PolicyT2<16, 2, 2>;    // t=2, BM 256
-using V4 = PolicyT2<16, 1, 1>;    // t=2, BM 128
+template <int K> using V1 = PolicyT2<16, 8, 2, K>;   // t=2, BM 1024
+template <int K> using V2 = PolicyT2<16, 4, 4, K>;   // t=2, BM 512
+template <int K> using V3 = PolicyT2<16, 2, 2, K>;   // t=2, BM 256
+template <int K> using V4 = PolicyT2<16, 1, 1, K>;   // t=2, BM 128
 using V5 = PolicyT1<16, 48>;      // t=1, BM 768 x 2048 columns
 using V6 = PolicyT1<16, 32>;      // t=1, BM 512
 using V7 = PolicyT2<8, 4, 4>;     // t=2, BM 256, 8 waves
@@ -1035,31 +1050,74 @@ using V8 = PolicyT1<8, 32>;       // t=1, BM 256, 8 waves
 using V9 = PolicyT1<4, 32>;       // t=1, BM 128, 4 waves
 using V10 = PolicyT2<16, 11, 2>;  // t=2, BM 1408: six tiles cover 8192 rows
 using V11 = PolicyT8<16, 4>;      // t=8, BM 2048 x 256 columns (narrow products)
-using V12 = PolicyT8<16, 2>;      // t=8, BM 1024
-using V13 = PolicyT8<16, 1>;      // t=8, BM 512
+template <int K> using V12 = PolicyT8<16, 2, K>;     // t=8, BM 1024
+template <int K> using V13 = PolicyT8<16, 1, K>;     // t=8, BM 512
 using V14 = PolicyT32<16, 4>;     // t=32, BM 1024 x 64 columns (matrix-vector, n <= 64)
 using V15 = PolicyT32<16, 2>;     // t=32, BM 512
 using V16 = PolicyT4<16, 8>;      // t=4, BM 2048 x 512 columns: four tiles cover 8192 rows
 using V17 = PolicyT4<16, 6>;      // t=4, BM 1536
-using V18 = PolicyT4<16, 4>;      // t=4, BM 1024
-#define GF2_V(P) { P::NT, P::BM, P::TW, P::PR, m4rm_group<P>, m4rm_list<P> }
-const Variant kVariants[] = {GF2_V(V0), GF2_V(V1), GF2_V(V2), GF2_V(V3), GF2_V(V4),
-                             GF2_V(V5), GF2_V(V6), GF2_V(V7), GF2_V(V8), GF2_V(V9), GF2_V(V10),
-                             GF2_V(V11), GF2_V(V12), GF2_V(V13), GF2_V(V14), GF2_V(V15),
-                             GF2_V(V16), GF2_V(V17), GF2_V(V18)};
-#undef GF2_V
+template <int K> using V18 = PolicyT4<16, 4, K>;     // t=4, BM 1024
+template <int K> using V19 = PolicyT4<16, 2, K>;     // t=4, BM 512
+template <int K> using V20 = PolicyT4<16, 1, K>;     // t=4, BM 256
+const Variant kVariants[] = {variant8<V0>(), variantk<V1>(), variantk<V2>(), variantk<V3>(), variantk<V4>(),
+                             variant8<V5>(), variant8<V6>(), variant8<V7>(), variant8<V8>(), variant8<V9>(),
+                             variant8<V10>(), variant8<V11>(), variantk<V12>(), variantk<V13>(), variant8<V14>(),
+                             variant8<V15>(), variant8<V16>(), variant8<V17>(), variantk<V18>(), variantk<V19>(),
+                             variantk<V20>()};
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
+// The persistent kernel's tables, at file scope so that the tile functions below address
+// them as LDS directly.
+__shared__ uint4 g_ptab[2 * TABLE_BYTES / 16];
+
+__device__ __forceinline__ int64_t uniform64(int64_t x) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)x >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+template <class T>
+__device__ __forceinline__ T* uniform_ptr(T* p) { return reinterpret_cast<T*>(uniform64((int64_t)p)); }
+
+// One tile of the persistent kernel, compiled as a function of its own: inlined together, the
+// tile families' register allocations merge and spill, while each alone fits.  Arguments of a
+// device function arrive in vector registers; the descriptor is uniform, so its fields are
+// moved back to scalar registers before use.
+template <class P>
+__device__ __noinline__ void persistent_tile(MulDesc d, int tm, int tn) {
+  MulDesc u;
+  u.A = uniform_ptr(d.A);
+  u.B = uniform_ptr(d.B);
+  u.C = uniform_ptr(d.C);
+  u.lda = uniform64(d.lda);
+  u.ldb = uniform64(d.ldb);
+  u.ldc = uniform64(d.ldc);
+  u.m = __builtin_amdgcn_readfirstlane(d.m);
+  u.k = __builtin_amdgcn_readfirstlane(d.k);
+  u.n = __builtin_amdgcn_readfirstlane(d.n);
+  u.out = __builtin_amdgcn_readfirstlane(d.out);
+  P::run(u, __builtin_amdgcn_readfirstlane(tm), __builtin_amdgcn_readfirstlane(tn), reinterpret_cast<char*>(g_ptab));
+}
+
+template <template <int> class F>
+__device__ __forceinline__ void run_kappa(int kappa, const MulDesc& d, int tm, int tn) {
+  switch (kappa) {
+    case 4: persistent_tile<F<4>>(d, tm, tn); break;
+    case 5: persistent_tile<F<5>>(d, tm, tn); break;
+    case 6: persistent_tile<F<6>>(d, tm, tn); break;
+    case 7: persistent_tile<F<7>>(d, tm, tn); break;
+    default: persistent_tile<F<8>>(d, tm, tn); break;
+  }
+}
+
 // Persistent batch kernel: one workgroup per compute unit pulls tile items from an
-// atomic queue (ordered longest first) until it runs dry; every item names its product
-// and one of the 16-wave variants.  Each tile ends on a barrier, so LDS is free for the
-// next item.
+// atomic queue (ordered longest first) until it runs dry; every item names its product,
+// one of the 16-wave variants of at most 1024 rows (two, four or eight tables per phase)
+// and its table width (variant | width << 8).  Each tile ends on a barrier, so LDS is free
+// for the next item.
 __global__ __launch_bounds__(1024) void m4rm_persistent(const MulDesc* __restrict__ ds,
                                                         const BatchItem* __restrict__ items, int nitems,
                                                         int* __restrict__ counter) {
-  __shared__ uint4 tab[2 * TABLE_BYTES / 16];
   __shared__ int next;
-  char* t = reinterpret_cast<char*>(tab);
   for (;;) {
     if (threadIdx.x == 0) next = atomicAdd(counter, 1);
     __syncthreads();
@@ -1068,32 +1126,118 @@ __global__ __launch_bounds__(1024) void m4rm_persistent(const MulDesc* __restric
     if (i >= nitems) break;
     const BatchItem it = items[i];
     const MulDesc d = ds[it.desc];
-    switch (it.variant) {
-      case 1: V1::run(d, it.tm, it.tn, t); break;
-      case 2: V2::run(d, it.tm, it.tn, t); break;
-      case 3: V3::run(d, it.tm, it.tn, t); break;
-      default: V4::run(d, it.tm, it.tn, t); break;
+    const int kappa = it.variant >> 8;
+    switch (it.variant & 0xff) {
+      case 1: run_kappa<V1>(kappa, d, it.tm, it.tn); break;
+      case 2: run_kappa<V2>(kappa, d, it.tm, it.tn); break;
+      case 3: run_kappa<V3>(kappa, d, it.tm, it.tn); break;
+      case 12: run_kappa<V12>(kappa, d, it.tm, it.tn); break;
+      case 13: run_kappa<V13>(kappa, d, it.tm, it.tn); break;
+      case 18: run_kappa<V18>(kappa, d, it.tm, it.tn); break;
+      case 19: run_kappa<V19>(kappa, d, it.tm, it.tn); break;
+      case 20: run_kappa<V20>(kappa, d, it.tm, it.tn); break;
+      default: run_kappa<V4>(kappa, d, it.tm, it.tn); break;
     }
   }
 }
 
 __global__ void reset_counter(int* c) { *c = 0; }
 
+// Index expansion of A for a table narrower than 8 bits (Section 3: with a table of kappa
+// index bits, row r's stripe j is selected by bits kappa*j .. kappa*j + kappa - 1 of A's row).
+// Byte j of row r of X holds that field (its bit 0 = column kappa*j); bits of A at or past k
+// read as zero and X's bytes past ceil(k / kappa), up to the row's ldx words, are written 0, so
+// the M4RM tiles read one index byte per lookup whatever the width.  One block per row at a
+// time, one dword of X per thread.
+__device__ __forceinline__ void expand_rows(const ExpandOp& o) {
+  const int dws = (int)(2 * o.ldx);
+  const int kw = (int)words(o.k);
+  for (int64_t r = blockIdx.x; r < o.m; r += gridDim.x) {
+    const uint64_t* row = o.A + r * o.lda;
+    uint32_t* dst = reinterpret_cast<uint32_t*>(o.X + r * o.ldx);
+    for (int j = threadIdx.x; j < dws; j += blockDim.x) {
+      uint32_t out = 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t bit = (int64_t)(4 * j + q) * o.kappa;
+        if (bit < o.k) {
+          const int w = (int)(bit >> 6), sh = (int)(bit & 63);
+          uint64_t v = row[w] >> sh;
+          if (sh + o.kappa > 64 && w + 1 < kw) v |= row[w + 1] << (64 - sh);
+          const int64_t nb = imin64(o.kappa, o.k - bit);
+          out |= (uint32_t)(v & ((1ull << nb) - 1)) << (8 * q);
+        }
+      }
+      dst[j] = out;
+    }
+  }
+}
+
+constexpr int kExpandOps = 64;
+struct ExpandArgs {
+  ExpandOp op[kExpandOps];
+  int count;
+};
+
+__global__ __launch_bounds__(256) void expand_group(ExpandArgs a) { expand_rows(a.op[blockIdx.y]); }
+__global__ __launch_bounds__(256) void expand_list(const ExpandOp* __restrict__ ops) { expand_rows(ops[blockIdx.y]); }
+
 const Variant& variant_of(int v) { return kVariants[(v < 0 || v >= kNumVariants) ? 0 : v]; }
+
+unsigned expand_grid_x(int64_t max_rows) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>(max_rows, 1024)); }
 
 }  // namespace
 
 int m4rm_num_variants() { return kNumVariants; }
 int m4rm_tile_rows(int variant) { return variant_of(variant).bm; }
 int m4rm_tile_words(int variant) { return variant_of(variant).tw; }
-int m4rm_phase_rows(int variant) { return variant_of(variant).pr; }
+int m4rm_phase_rows(int variant, int kappa) { return variant_of(variant).pr / KB * kappa; }
+bool m4rm_has_kappa(int variant, int kappa) {
+  return kappa >= kKappaMin && kappa <= KB && variant >= 0 && variant < kNumVariants &&
+         variant_of(variant).group[kappa - kKappaMin] != nullptr;
+}
 
 int64_t m4rm_tiles(const MulDesc& d, int variant) {
   const int64_t bm = variant_of(variant).bm, tw = variant_of(variant).tw;
   return ((d.m + bm - 1) / bm) * ((words(d.n) + tw - 1) / tw);
 }
 
-gf2_status m4rm_launch_group(const MulDesc* descs, int count, int variant, hipStream_t s, int tail) {
+int64_t m4rm_expanded_ld(int64_t k, int kappa) { return ((k + kappa - 1) / kappa + 7) / 8; }
+
+gf2_status m4rm_expand(const ExpandOp* ops, int n, hipStream_t s) {
+  for (int i = 0; i < n; i += kExpandOps) {
+    ExpandArgs a;
+    a.count = std::min(kExpandOps, n - i);
+    int64_t rows = 0;
+    for (int j = 0; j < a.count; ++j) {
+      a.op[j] = ops[i + j];
+      rows = std::max<int64_t>(rows, a.op[j].m);
+    }
+    hipLaunchKernelGGL(expand_group, dim3(expand_grid_x(rows), (unsigned)a.count), dim3(256), 0, s, a);
+    gf2_status st = hip_check(hipGetLastError(), "expand_group launch");
+    if (st != GF2_OK) return st;
+  }
+  return GF2_OK;
+}
+
+gf2_status m4rm_expand_list(const ExpandOp* dev_ops, int n, int64_t max_rows, hipStream_t s) {
+  for (int i = 0; i < n; i += 65535) {   // grid y limit
+    const int c = std::min(65535, n - i);
+    hipLaunchKernelGGL(expand_list, dim3(expand_grid_x(max_rows), (unsigned)c), dim3(256), 0, s, dev_ops + i);
+    gf2_status st = hip_check(hipGetLastError(), "expand_list launch");
+    if (st != GF2_OK) return st;
+  }
+  return GF2_OK;
+}
+
+gf2_status m4rm_launch_group(const MulDesc* descs, int count, int variant, hipStream_t s, int tail, int kappa) {
+  if (!m4rm_has_kappa(variant, kappa))
+    return set_error(GF2_ERR_UNSUPPORTED, "M4RM variant %d has no %d-bit tables", variant, kappa);
+  // A narrower table reads A's index expansion, whose rows the tiles address with 32-bit offsets.
+  if (kappa < KB)
+    for (int i = 0; i < count; ++i)
+      if (descs[i].lda >= (int64_t(1) << 20))
+        return set_error(GF2_ERR_UNSUPPORTED, "%d-bit tables need k below %lld", kappa, (long long)kappa << 23);
   // The one-word tile addresses 256 rows of B per phase with 32-bit offsets: for B rows of
   // 2^20 words or more the eight-table 512-row tile (same bits) runs instead.
   if (variant_of(variant).pr == P32)
@@ -1104,7 +1248,7 @@ gf2_status m4rm_launch_group(const MulDesc* descs, int count, int variant, hipSt
       }
   // The four-table tiles address up to 128 rows of A per wave the same way: for A rows of
   // 2^20 words or more the 1408-row two-table tile runs instead.
-  if (variant_of(variant).pr == P4)
+  if (variant_of(variant).tw == T4_WORDS)
     for (int i = 0; i < count; ++i)
       if (descs[i].lda >= (int64_t(1) << 20)) {
         variant = 10;
@@ -1132,16 +1276,22 @@ gf2_status m4rm_launch_group(const MulDesc* descs, int count, int variant, hipSt
     g.tile_start[g.count] = (int)total;
     if (g.remap_n < 0) g.remap_n = (int)total;
     double work = 0;
-    for (int j = 0; j < g.count; ++j) work += (double)g.d[j].m * ((g.d[j].k + KB - 1) / KB) * (double)words(g.d[j].n);
+    for (int j = 0; j < g.count; ++j)
+      work += (double)g.d[j].m * ((g.d[j].k + kappa - 1) / kappa) * (double)words(g.d[j].n);
     TraceScope trace(GF2_TRACE_M4RM, g.count, work, s);
-    hipLaunchKernelGGL(v.group, dim3((unsigned)total), dim3(v.threads), 0, s, g);
+    hipLaunchKernelGGL(v.group[kappa - kKappaMin], dim3((unsigned)total), dim3(v.threads), 0, s, g);
     gf2_status st = hip_check(hipGetLastError(), "m4rm_group launch");
     if (st != GF2_OK) return st;
   }
   return GF2_OK;
 }
 
-bool m4rm_batchable(int variant) { return variant >= 1 && variant <= 4; }
+bool m4rm_batchable(int variant) {
+  switch (variant) {
+    case 1: case 2: case 3: case 4: case 12: case 13: case 18: case 19: case 20: return true;
+    default: return false;
+  }
+}
 
 gf2_status m4rm_launch_persistent(const MulDesc* dev_descs, const BatchItem* dev_items, int nitems, int* dev_counter,
                                   int grid, hipStream_t s) {
@@ -1150,15 +1300,6 @@ gf2_status m4rm_launch_persistent(const MulDesc* dev_descs, const BatchItem* dev
   if (st != GF2_OK || nitems == 0) return st;
   hipLaunchKernelGGL(m4rm_persistent, dim3(grid), dim3(1024), 0, s, dev_descs, dev_items, nitems, dev_counter);
   return hip_check(hipGetLastError(), "m4rm_persistent launch");
-}
-
-gf2_status m4rm_launch_list(const MulDesc* dev_descs, const int* dev_tile_start, int count, int64_t total_tiles,
-                            int variant, hipStream_t s) {
-  if (total_tiles == 0 || count == 0) return GF2_OK;
-  if (total_tiles > INT32_MAX) return set_error(GF2_ERR_UNSUPPORTED, "m4rm: too many tiles");
-  const Variant& v = variant_of(variant);
-  hipLaunchKernelGGL(v.list, dim3((unsigned)total_tiles), dim3(v.threads), 0, s, dev_descs, dev_tile_start, count);
-  return hip_check(hipGetLastError(), "m4rm_list launch");
 }
 
 }  // namespace gf2

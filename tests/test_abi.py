@@ -109,12 +109,44 @@ def test_batch_validation_without_device():
 
 
 def test_schedule_struct_layout():
-    """gf2_schedule is five int32 fields (kernel, variant, cutoff, splitk, odd)."""
+    """gf2_schedule is six int32 fields (kernel, variant, cutoff, splitk, odd, kappa)."""
     import ctypes
     import paper_0811_1714_amd as g
-    assert ctypes.sizeof(g.Schedule) == 20
-    assert [f[0] for f in g.Schedule._fields_] == ["kernel", "variant", "cutoff", "splitk", "odd"]
+    assert ctypes.sizeof(g.Schedule) == 24
+    assert [f[0] for f in g.Schedule._fields_] == ["kernel", "variant", "cutoff", "splitk", "odd", "kappa"]
     assert (g.ODD_PAD, g.ODD_PEEL) == (0, 1)
+
+
+def test_table_width_validation_and_workspace():
+    """kappa 0 means 8; 4..7 only on the tiles of at most 1024 rows (the others, and widths outside
+    4..8, are refused); a narrow table's workspace holds A's index bytes, one per kappa bits of k,
+    rounded up to whole words per row, 256-byte aligned per product."""
+    import paper_0811_1714_amd as g
+    narrow = {1, 2, 3, 4, 12, 13, 18, 19, 20}
+    assert g.resolve_schedule(1000, 1000, 1000, g.Schedule(g.KERNEL_M4RM, 2, 0, 1)).kappa == 8
+    for v in range(g.kernel_variants(g.KERNEL_M4RM)):
+        for kappa in (4, 5, 6, 7, 8):
+            s = g.Schedule(g.KERNEL_M4RM, v, 0, 1, 0, kappa)
+            if kappa == 8 or v in narrow:
+                assert g.resolve_schedule(1000, 1000, 1000, s).kappa == kappa
+            else:
+                try:
+                    g.resolve_schedule(1000, 1000, 1000, s)
+                except g.GF2Error as e:
+                    assert e.status == 6, (v, kappa)
+                else:
+                    raise AssertionError(f"variant {v} accepted {kappa}-bit tables")
+    for bad in (1, 3, 9, -1):
+        try:
+            g.resolve_schedule(100, 100, 100, g.Schedule(g.KERNEL_M4RM, 2, 0, 1, 0, bad))
+        except g.GF2Error as e:
+            assert e.status == 1
+        else:
+            raise AssertionError(f"table width {bad} accepted")
+    # 1000 x 1000 at 6 bits: 167 index bytes -> 21 words per row; 21000 words, aligned to 32.
+    assert g.workspace_bytes(1000, 1000, 1000, g.Schedule(g.KERNEL_M4RM, 2, 0, 1, 0, 6)) == 21024 * 8
+    # k in four slices of 4 words: each slice's 256 bits give 52 bytes at 5 bits -> 7 words per row.
+    assert g.workspace_bytes(100, 1024, 500, g.Schedule(g.KERNEL_M4RM, 2, 0, 4, 0, 5)) == 4 * 704 * 8
 
 
 def test_peeling_workspace_is_sized_for_the_aligned_core():

@@ -20,9 +20,13 @@ def g():
     return g
 
 
-def M4RM(variant=0, cutoff=0, splitk=1, odd=0):
+def M4RM(variant=0, cutoff=0, splitk=1, odd=0, kappa=0):
     import paper_0811_1714_amd as g
-    return g.Schedule(g.KERNEL_M4RM, variant, cutoff, splitk, odd)
+    return g.Schedule(g.KERNEL_M4RM, variant, cutoff, splitk, odd, kappa)
+
+
+# Tiles that offer tables narrower than 8 bits (Section 3.1's k): every tile of at most 1024 rows.
+KAPPA_VARIANTS = (1, 2, 3, 4, 12, 13, 18, 19, 20)
 
 
 def test_config_1024_square_plain_m4rm(g):
@@ -41,6 +45,34 @@ def test_shape_grid_all_variants(g, m, k, n):
     for v in range(g.kernel_variants(g.KERNEL_M4RM)):
         print(f"shape {(m, k, n)} variant {v}", flush=True)
         run_and_check(g, m, k, n, schedule=M4RM(v), seed=m + k + n, lda_pad=1, ldb_pad=3, ldc_pad=2)
+
+
+@pytest.mark.parametrize("m,k,n", SHAPES)
+def test_shape_grid_narrow_tables(g, m, k, n):
+    """Every tile with narrow tables at every width 4..7: A's kappa-bit fields become index bytes
+    (fields straddling words, a last field cut short by k, garbage padding bits past k)."""
+    for v in KAPPA_VARIANTS:
+        for kappa in (4, 5, 6, 7):
+            print(f"shape {(m, k, n)} variant {v} kappa {kappa}", flush=True)
+            run_and_check(g, m, k, n, schedule=M4RM(v, kappa=kappa), seed=m + k + n + kappa, lda_pad=1, ldb_pad=3,
+                          ldc_pad=2)
+
+
+@pytest.mark.parametrize("shape,sched", [
+    ((1000, 1000, 1000), (2, 100, 1, 0, 5)),        # two Strassen levels over 5-bit tables
+    ((1025, 1023, 1021), (1, 256, 1, 1, 7)),        # peeling: inner-slice and edge fix-ups expanded too
+    ((300, 1000, 3000), (3, 0, 4, 0, 6)),           # k in four slices, each expanded on its own
+    ((4095, 65537, 129), (13, 0, 1, 0, 4)),         # long k: 16385 index bytes per row
+    ((2047, 31, 4097), (19, 0, 1, 0, 5)),           # k shorter than one phase
+])
+def test_narrow_tables_with_recursion_split_and_peeling(g, shape, sched):
+    m, k, n = shape
+    v, cutoff, sk, odd, kappa = sched
+    print(f"narrow {(m, k, n)} variant {v} cutoff {cutoff} splitk {sk} odd {odd} kappa {kappa}", flush=True)
+    base = run_and_check(g, m, k, n, schedule=M4RM(v, cutoff, sk, odd, kappa), seed=21, lda_pad=2, ldc_pad=1)
+    wide = run_and_check(g, m, k, n, schedule=M4RM(v, cutoff, sk, odd), seed=21, lda_pad=2, ldc_pad=1)
+    assert np.array_equal(base, wide)
+    run_and_check(g, m, k, n, schedule=M4RM(v, cutoff, sk, odd, kappa), accumulate=True, seed=22, ldb_pad=1)
 
 
 @pytest.mark.parametrize("m,k,n", [(100, 300, 70), (513, 2048, 2100), (64, 65, 4096)])

@@ -1,6 +1,6 @@
 """Seeded random cross-checks of the whole product path against the CPU oracle: random
 shapes (log-uniform in [8, 5000], one in five in [1000, 6000]), densities, strides and modes under random schedules
-(any base kernel and tile variant, Strassen-Winograd cutoff, odd-size rule and k split).
+(any base kernel and tile variant, Strassen-Winograd cutoff, odd-size rule, k split and M4RM table width).
 Every result must be bit-exact whatever the schedule."""
 import numpy as np
 import pytest
@@ -29,9 +29,15 @@ def random_case(rng, g):
     cutoff = 0 if rng.uniform() < 0.4 else max(64, int(min(m, k, n) / 2 ** rng.uniform(0.5, 3)))
     splitk = 1 if rng.uniform() < 0.6 else int(rng.integers(2, 9))
     odd = int(rng.integers(2)) if cutoff else 0
-    return dict(m=m, k=k, n=n, schedule=(kernel, variant, cutoff, splitk, odd),
-                accumulate=bool(rng.integers(2)), p=float(rng.choice([0.5, 0.1, 0.01])),
-                lda_pad=int(rng.integers(3)), ldb_pad=int(rng.integers(3)), ldc_pad=int(rng.integers(3)))
+    c = dict(m=m, k=k, n=n, accumulate=bool(rng.integers(2)), p=float(rng.choice([0.5, 0.1, 0.01])),
+             lda_pad=int(rng.integers(3)), ldb_pad=int(rng.integers(3)), ldc_pad=int(rng.integers(3)))
+    # Table width: 8, or 4..7 on the tiles that offer narrow tables.
+    kappa = int(rng.choice([0, 4, 5, 6, 7])) if kernel == g.KERNEL_M4RM and variant in NARROW else 0
+    c["schedule"] = (kernel, variant, cutoff, splitk, odd, kappa)
+    return c
+
+
+NARROW = (1, 2, 3, 4, 12, 13, 18, 19, 20)   # tiles with tables of 4..7 bits
 
 
 def case(i, g):
