@@ -243,7 +243,8 @@ def configs_bench(g):
         torch.cuda.empty_cache()
 
 
-ABLATION = ((5, "one table per 8-row stripe (Alg. 2), 768 x 2048"), (6, "one table, 512 x 2048"),
+ABLATION = ((21, "one table per 8-row stripe for all m rows, C in global memory (Alg. 1), n/64 workgroups"),
+            (5, "one table per 8-row stripe (Alg. 2), 768 x 2048"), (6, "one table, 512 x 2048"),
             (0, "t = 2 (Alg. 3), 1536 x 1024"), (10, "t = 2, 1408 x 1024"), (1, "t = 2, 1024 x 1024"),
             (2, "t = 2, 512 x 1024"), (11, "t = 8 (Alg. 3), 2048 x 256"), (12, "t = 8, 1024 x 256"),
             (13, "t = 8, 512 x 256"), (16, "t = 4 (Alg. 3), 2048 x 512"), (17, "t = 4, 1536 x 512"),
@@ -569,6 +570,17 @@ def main():
 
     C = dC.cpu().numpy().view(np.uint64)    # the timed product; the CPU leg compares rows of it
 
+    # Workspace of the timed (breadth-first) plan, and of the same schedule with Section 4's
+    # two-temporary form at the top level, timed too and compared with the timed product.
+    workspace = {"bytes": ws, "operand_bytes": 3 * n * ((n + 63) // 64) * 8}
+    if args.kernel == "m4rm" and sched.cutoff:
+        low = g.Schedule(sched.kernel, sched.variant, sched.cutoff, sched.splitk, sched.odd, sched.kappa, g.MEM_LOW)
+        fast_c = dC.clone()
+        low_ms, _ = time_product(g, dA, dB, dC, n, low, max(3, args.steps // 2), 2)
+        workspace["two_temporary"] = {"bytes": g.workspace_bytes(n, n, n, low), "ms_per_step": low_ms,
+                                      "same_bits": bool(torch.equal(fast_c, dC))}
+        del fast_c
+
     if args.kernel == "mfma":
         mf = [r for r in recs if r[0] == "mfma"]
         launches = len(mf)
@@ -631,6 +643,7 @@ def main():
                                         "splitk": sched.splitk},
                    "ms_min": min(per), "ms_median": float(np.median(per)), "bit_exact_sampled_rows": None},
         "roofline": roofline,
+        "workspace": workspace,
     }
     if args.batch:
         del dA, dB, dC

@@ -75,9 +75,17 @@ enum {
  * inner slice with non-recursive base-case products. */
 enum { GF2_ODD_PAD = 0, GF2_ODD_PEEL = 1 };
 
+/* Workspace plan of Strassen-Winograd (Section 4).  FAST: every node's temporaries
+ * (S0..S3, T0..T3, P0..P6) exist at once and all leaves of the product run in one launch.
+ * LOW: at the top level, the memory-efficient schedule with two temporaries X (m/2 x
+ * max(k, n)/2) and Y (k/2 x n/2): the seven products run one after another, written
+ * straight into C's quadrants (each computed FAST below), with the additions between
+ * them.  LOW applies to C := A*B with m even and n a multiple of 128; other calls run FAST. */
+enum { GF2_MEM_FAST = 0, GF2_MEM_LOW = 1 };
+
 /* A schedule: which base kernel, its tile variant, the Strassen-Winograd
- * crossover, the number of k slices, the odd-size rule and the M4RM table
- * width.  Zero fields mean "default". */
+ * crossover, the number of k slices, the odd-size rule, the M4RM table width
+ * and the workspace plan.  Zero fields mean "default". */
 typedef struct gf2_schedule {
   int32_t kernel;   /* GF2_KERNEL_* */
   int32_t variant;  /* kernel tile variant (see gf2_kernel_variants) */
@@ -89,6 +97,7 @@ typedef struct gf2_schedule {
                      * 18-20; others give GF2_ERR_UNSUPPORTED).  With kappa < 8 each base-case
                      * product first writes its A's kappa-bit fields out as bytes into the
                      * workspace; k must stay below kappa * 2^23. */
+  int32_t memory;   /* GF2_MEM_FAST or GF2_MEM_LOW (only with cutoff > 0) */
 } gf2_schedule;
 
 /* C := A*B.  Section 1 / Section 2.3 definition above.  m, k, n >= 0.
@@ -235,8 +244,9 @@ gf2_status gf2_resolve_schedule(int64_t m, int64_t k, int64_t n, const gf2_sched
 /* Number of tile variants of a base kernel (0 for an unknown kernel). */
 int32_t gf2_kernel_variants(int32_t kernel);
 
-/* Device workspace, in bytes, that a product of this shape under `sched` uses
- * (Strassen temporaries and split-K partials; 0 when none). */
+/* Device workspace, in bytes, that C := A*B of this shape under `sched` uses
+ * (Strassen temporaries, narrow-table index bytes, base-kernel scratch; 0 when
+ * none).  C := C + A*B always plans GF2_MEM_FAST: size it with memory = FAST. */
 size_t gf2_workspace_bytes(int64_t m, int64_t k, int64_t n, const gf2_schedule* sched);
 
 /* Grow the current device's workspace to at least `bytes` now (synchronising

@@ -19,6 +19,7 @@ _LIB = None
 
 KERNEL_AUTO, KERNEL_M4RM, KERNEL_MFMA, KERNEL_CUBIC = 0, 1, 2, 3
 ODD_PAD, ODD_PEEL = 0, 1
+MEM_FAST, MEM_LOW = 0, 1
 
 STATUS = {0: "GF2_OK", 1: "GF2_ERR_INVALID_ARG", 2: "GF2_ERR_ALIAS", 3: "GF2_ERR_ALLOC", 4: "GF2_ERR_CAPTURE",
           5: "GF2_ERR_DEVICE", 6: "GF2_ERR_UNSUPPORTED"}
@@ -32,11 +33,12 @@ class GF2Error(RuntimeError):
 
 class Schedule(ctypes.Structure):
     _fields_ = [("kernel", ctypes.c_int32), ("variant", ctypes.c_int32), ("cutoff", ctypes.c_int32),
-                ("splitk", ctypes.c_int32), ("odd", ctypes.c_int32), ("kappa", ctypes.c_int32)]
+                ("splitk", ctypes.c_int32), ("odd", ctypes.c_int32), ("kappa", ctypes.c_int32),
+                ("memory", ctypes.c_int32)]
 
     def __repr__(self):
         return (f"Schedule(kernel={self.kernel}, variant={self.variant}, cutoff={self.cutoff}, "
-                f"splitk={self.splitk}, odd={self.odd}, kappa={self.kappa})")
+                f"splitk={self.splitk}, odd={self.odd}, kappa={self.kappa}, memory={self.memory})")
 
 
 def lib():
@@ -167,6 +169,14 @@ def mul_ptr(C, ldc, A, lda, B, ldb, m, k, n, *, accumulate=False, schedule=None,
 
 
 NOALLOC_SCRATCH_BYTES = 64 << 20   # GF2_NOALLOC_SCRATCH_BYTES
+# M4RM tile variants the persistent batch kernel runs (the candidates a batch may use).
+BATCH_VARIANTS = (1, 2, 3, 4, 12, 13, 18, 19, 20)
+
+
+def batch_candidate(index):
+    """True when candidate ``index`` runs inside the persistent batch kernel."""
+    c = candidate(index)
+    return c.kernel == KERNEL_M4RM and c.variant in BATCH_VARIANTS
 
 
 def mul_noalloc_ptr(C, ldc, A, lda, B, ldb, m, k, n, *, accumulate=False, schedule=None, stream=None):

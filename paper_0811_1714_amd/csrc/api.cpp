@@ -308,6 +308,7 @@ gf2_schedule resolve(const gf2_schedule* req, int64_t m, int64_t k, int64_t n, h
     if (req->splitk > 0) s.splitk = req->splitk;
     s.odd = req->odd;
     s.kappa = req->kappa;
+    s.memory = req->memory;
   }
   if (s.kappa <= 0) s.kappa = 8;
   return s;
@@ -360,6 +361,8 @@ gf2_status validate_sched(const gf2_schedule* s) {
   if (s->odd != GF2_ODD_PAD && s->odd != GF2_ODD_PEEL) return set_error(GF2_ERR_INVALID_ARG, "unknown odd-size rule %d", s->odd);
   if (s->kappa != 0 && (s->kappa < 4 || s->kappa > 8))
     return set_error(GF2_ERR_INVALID_ARG, "table width %d outside 4..8", s->kappa);
+  if (s->memory != GF2_MEM_FAST && s->memory != GF2_MEM_LOW)
+    return set_error(GF2_ERR_INVALID_ARG, "unknown workspace plan %d", s->memory);
   if (s->kernel == GF2_KERNEL_M4RM && s->kappa != 0 && !m4rm_has_kappa(s->variant, s->kappa))
     return set_error(GF2_ERR_UNSUPPORTED, "M4RM variant %d has no %d-bit tables", s->variant, s->kappa);
   return GF2_OK;
@@ -661,10 +664,47 @@ void plan_product(ProductPlan& pp, uint64_t* base, uint64_t* C, int64_t ldc, con
   pp.scratch_words = base_scratch_words(s, all);
 }
 
-size_t workspace_words(int64_t m, int64_t k, int64_t n, const gf2_schedule& s) {
+size_t fast_workspace_words(int64_t m, int64_t k, int64_t n, const gf2_schedule& s) {
   ProductPlan pp;
   plan_product(pp, nullptr, nullptr, words(n), nullptr, words(k), nullptr, words(n), m, k, n, false, s);
   return pp.total_words();
+}
+
+// Section 4's memory-efficient schedule at the top level (GF2_MEM_LOW): C := A*B with equal
+// halves of rows and of (word-aligned) columns, so that each of the seven products fits the
+// C quadrant it is written to.
+bool two_temp_applies(int64_t m, int64_t k, int64_t n, bool accumulate, const gf2_schedule& s) {
+  return s.memory == GF2_MEM_LOW && !accumulate && splittable(m, k, n, s.cutoff) && m % 2 == 0 && n % 128 == 0;
+}
+
+struct TwoTemp {
+  int64_t m0, k0w, k0, k1, n0w;
+  size_t x_words, y_words, sub_words;
+  gf2_schedule sub;   // the products below the top level: FAST
+};
+
+TwoTemp two_temp_plan(int64_t m, int64_t k, int64_t n, const gf2_schedule& s) {
+  TwoTemp t;
+  t.m0 = m / 2;
+  t.k0w = (words(k) + 1) / 2;
+  t.k0 = 64 * t.k0w;
+  t.k1 = k - t.k0;
+  t.n0w = words(n) / 2;
+  t.sub = s;
+  t.sub.memory = GF2_MEM_FAST;
+  t.x_words = align_words((size_t)(t.m0 * std::max(t.k0w, t.n0w)));
+  t.y_words = align_words((size_t)(t.k0 * t.n0w));
+  t.sub_words = std::max(fast_workspace_words(t.m0, t.k0, 64 * t.n0w, t.sub),
+                         fast_workspace_words(t.m0, t.k1, 64 * t.n0w, t.sub));
+  return t;
+}
+
+size_t workspace_words(int64_t m, int64_t k, int64_t n, const gf2_schedule& s, bool accumulate = false) {
+  if (two_temp_applies(m, k, n, accumulate, s)) {
+    const TwoTemp t = two_temp_plan(m, k, n, s);
+    return t.x_words + t.y_words + t.sub_words;
+  }
+  return fast_workspace_words(m, k, n, s);
 }
 
 // Launches of one product whose workspace (Strassen temporaries, then the base kernel's
@@ -712,14 +752,92 @@ gf2_status execute_in(uint64_t* C, int64_t ldc, const uint64_t* A, int64_t lda, 
   return run_base(s, pp.leaves, scratch, st);
 }
 
+// The two-temporary schedule (Section 4, memory-efficient form; every addition is XOR):
+//   X = S2 = A_NW + A_SW,  Y = T2 = B_SE + B_NE,  C_SW = P6 = X Y
+//   X = S0 = A_SW + A_SE,  Y = T0 = B_NE + B_NW,  C_SE = P4 = X Y
+//   X = S1 = X + A_NW,     Y = T1 = B_SE + Y,     C_NE = P5 = X Y
+//   X = S3 = A_NE + X,     C_NW = P2 = X B_SE,    X = P0 = A_NW B_NW
+//   C_NE = U1 = X + C_NE,  C_SW = U2 = C_NE + C_SW,  C_NE = U3 = C_NE + C_SE,
+//   C_SE = U6 = C_SW + C_SE,  C_NE = U4 = C_NE + C_NW
+//   Y = T3 = Y + B_SW,     C_NW = P3 = A_SE Y,    C_SW = U5 = C_SW + C_NW
+//   C_NW = P1 = A_NE B_SW, C_NW = U0 = X + C_NW
+// The products run breadth-first below (all their leaves in one launch) in the workspace
+// after X and Y, one after another.
+gf2_status execute_two_temp(uint64_t* C, int64_t ldc, const uint64_t* A, int64_t lda, const uint64_t* B,
+                            int64_t ldb, int64_t m, int64_t k, int64_t n, const gf2_schedule& s, hipStream_t st,
+                            uint64_t* ws) {
+  const TwoTemp t = two_temp_plan(m, k, n, s);
+  const int64_t m0 = t.m0, k0w = t.k0w, k0 = t.k0, k1 = t.k1, n0w = t.n0w, n0 = 64 * n0w;
+  uint64_t* X = ws;
+  uint64_t* Y = ws + t.x_words;
+  uint64_t* sub = Y + t.y_words;
+  const uint64_t* A_NW = A;
+  const uint64_t* A_NE = A + k0w;
+  const uint64_t* A_SW = A + m0 * lda;
+  const uint64_t* A_SE = A + m0 * lda + k0w;
+  const uint64_t* B_NW = B;
+  const uint64_t* B_NE = B + n0w;
+  const uint64_t* B_SW = B + k0 * ldb;
+  const uint64_t* B_SE = B + k0 * ldb + n0w;
+  uint64_t* C_NW = C;
+  uint64_t* C_NE = C + n0w;
+  uint64_t* C_SW = C + m0 * ldc;
+  uint64_t* C_SE = C + m0 * ldc + n0w;
+  const uint64_t k1t = tail_of(k1);
+  const QView qA_NW{A_NW, lda, m0, k0w, ~0ull}, qA_NE{A_NE, lda, m0, words(k1), k1t};
+  const QView qA_SW{A_SW, lda, m0, k0w, ~0ull}, qA_SE{A_SE, lda, m0, words(k1), k1t};
+  const QView qB_NW{B_NW, ldb, k0, n0w, ~0ull}, qB_NE{B_NE, ldb, k0, n0w, ~0ull};
+  const QView qB_SW{B_SW, ldb, k1, n0w, ~0ull}, qB_SE{B_SE, ldb, k1, n0w, ~0ull};
+  const OView oX{X, k0w, m0, k0w, ~0ull}, oY{Y, n0w, k0, n0w, ~0ull};
+  const QView qX{X, k0w, m0, k0w, ~0ull}, qY{Y, n0w, k0, n0w, ~0ull}, qP0{X, n0w, m0, n0w, ~0ull};
+  const OView oNW{C_NW, ldc, m0, n0w, ~0ull}, oNE{C_NE, ldc, m0, n0w, ~0ull};
+  const OView oSW{C_SW, ldc, m0, n0w, ~0ull}, oSE{C_SE, ldc, m0, n0w, ~0ull};
+  const QView qNW{C_NW, ldc, m0, n0w, ~0ull}, qNE{C_NE, ldc, m0, n0w, ~0ull};
+  const QView qSW{C_SW, ldc, m0, n0w, ~0ull}, qSE{C_SE, ldc, m0, n0w, ~0ull};
+  auto prod = [&](uint64_t* c, int64_t lc, const uint64_t* a, int64_t la, const uint64_t* b, int64_t lb, int64_t kk) {
+    return execute_in(c, lc, a, la, b, lb, m0, kk, n0, false, t.sub, st, sub);
+  };
+  gf2_status r;
+  if ((r = xor2(oX, qA_NW, qA_SW, GF2_TRACE_PRE, st)) != GF2_OK) return r;     // S2
+  if ((r = xor2(oY, qB_SE, qB_NE, GF2_TRACE_PRE, st)) != GF2_OK) return r;     // T2
+  if ((r = prod(C_SW, ldc, X, k0w, Y, n0w, k0)) != GF2_OK) return r;           // P6
+  if ((r = xor2(oX, qA_SW, qA_SE, GF2_TRACE_PRE, st)) != GF2_OK) return r;     // S0
+  if ((r = xor2(oY, qB_NE, qB_NW, GF2_TRACE_PRE, st)) != GF2_OK) return r;     // T0
+  if ((r = prod(C_SE, ldc, X, k0w, Y, n0w, k0)) != GF2_OK) return r;           // P4
+  if ((r = xor2(oX, qX, qA_NW, GF2_TRACE_PRE, st)) != GF2_OK) return r;        // S1
+  if ((r = xor2(oY, qB_SE, qY, GF2_TRACE_PRE, st)) != GF2_OK) return r;        // T1
+  if ((r = prod(C_NE, ldc, X, k0w, Y, n0w, k0)) != GF2_OK) return r;           // P5
+  if ((r = xor2(oX, qA_NE, qX, GF2_TRACE_PRE, st)) != GF2_OK) return r;        // S3
+  if ((r = prod(C_NW, ldc, X, k0w, B_SE, ldb, k1)) != GF2_OK) return r;        // P2
+  if ((r = prod(X, n0w, A_NW, lda, B_NW, ldb, k0)) != GF2_OK) return r;        // P0 into X
+  if ((r = xor2(oNE, qP0, qNE, GF2_TRACE_POST, st)) != GF2_OK) return r;       // U1
+  if ((r = xor2(oSW, qNE, qSW, GF2_TRACE_POST, st)) != GF2_OK) return r;       // U2
+  if ((r = xor2(oNE, qNE, qSE, GF2_TRACE_POST, st)) != GF2_OK) return r;       // U3
+  if ((r = xor2(oSE, qSW, qSE, GF2_TRACE_POST, st)) != GF2_OK) return r;       // U6
+  if ((r = xor2(oNE, qNE, qNW, GF2_TRACE_POST, st)) != GF2_OK) return r;       // U4
+  if ((r = xor2(oY, qY, qB_SW, GF2_TRACE_PRE, st)) != GF2_OK) return r;        // T3
+  if ((r = prod(C_NW, ldc, A_SE, lda, Y, n0w, k1)) != GF2_OK) return r;        // P3
+  if ((r = xor2(oSW, qSW, qNW, GF2_TRACE_POST, st)) != GF2_OK) return r;       // U5
+  if ((r = prod(C_NW, ldc, A_NE, lda, B_SW, ldb, k1)) != GF2_OK) return r;     // P1
+  return xor2(oNW, qP0, qNW, GF2_TRACE_POST, st);                              // U0
+}
+
+// A product in the workspace at ``ws`` (workspace_words of it): two-temporary or breadth-first.
+gf2_status execute_ws(uint64_t* C, int64_t ldc, const uint64_t* A, int64_t lda, const uint64_t* B, int64_t ldb,
+                      int64_t m, int64_t k, int64_t n, bool accumulate, const gf2_schedule& s, hipStream_t st,
+                      uint64_t* ws) {
+  if (two_temp_applies(m, k, n, accumulate, s)) return execute_two_temp(C, ldc, A, lda, B, ldb, m, k, n, s, st, ws);
+  return execute_in(C, ldc, A, lda, B, ldb, m, k, n, accumulate, s, st, ws);
+}
+
 gf2_status execute(uint64_t* C, int64_t ldc, const uint64_t* A, int64_t lda, const uint64_t* B, int64_t ldb,
                    int64_t m, int64_t k, int64_t n, bool accumulate, const gf2_schedule& s, hipStream_t st) {
-  const size_t need = workspace_words(m, k, n, s) * 8;
+  const size_t need = workspace_words(m, k, n, s, accumulate) * 8;
   WorkspaceLease lease;
   gf2_status r = GF2_OK;
   if (need > 0 && (r = lease.acquire(need, st)) != GF2_OK) return r;
   if (need > 0) lease.used();
-  return execute_in(C, ldc, A, lda, B, ldb, m, k, n, accumulate, s, st, static_cast<uint64_t*>(lease.ptr()));
+  return execute_ws(C, ldc, A, lda, B, ldb, m, k, n, accumulate, s, st, static_cast<uint64_t*>(lease.ptr()));
 }
 
 int num_candidates_fwd() { return num_candidates(); }
@@ -885,13 +1003,13 @@ gf2_status mul_in_static(uint64_t* C, int64_t ldc, const uint64_t* A, int64_t ld
   if (k == 0) return accumulate ? GF2_OK : fill_zero(OView{C, ldc, m, words(n), tail_of(n)}, st);
   const gf2_schedule s = resolve(sched, m, k, n, st, false);
   if ((r = check_resolved(s)) != GF2_OK) return r;
-  const size_t need = workspace_words(m, k, n, s) * 8;
+  const size_t need = workspace_words(m, k, n, s, accumulate) * 8;
   if (need > max_bytes)
     return set_error(GF2_ERR_UNSUPPORTED,
                      "%lld x %lld x %lld under schedule (kernel %d, variant %d, cutoff %d, splitk %d) needs %zu bytes "
                      "of workspace; the static scratch holds %zu (choose a schedule with less recursion)",
                      (long long)m, (long long)k, (long long)n, s.kernel, s.variant, s.cutoff, s.splitk, need, max_bytes);
-  return execute_in(C, ldc, A, lda, B, ldb, m, k, n, accumulate, s, st, need > 0 ? ws : nullptr);
+  return execute_ws(C, ldc, A, lda, B, ldb, m, k, n, accumulate, s, st, need > 0 ? ws : nullptr);
 }
 
 namespace {
@@ -915,7 +1033,7 @@ struct BatchPlanImpl {
   std::vector<PostOp> post;
   std::vector<ExpandOp> expands;     // index expansions of A (table width < 8), after the pre passes
   ExpandOp* d_expands = nullptr;
-  int64_t expand_rows = 0;
+  int64_t expand_dwords = 0;        // largest expansion, in dwords (launch width)
   // Device copies, pre ops sorted by depth (parents first), post ops deepest first;
   // each group is one multi-op launch.
   OView* d_fills = nullptr;
@@ -953,7 +1071,7 @@ struct BatchPlanImpl {
         return r;
     for (const Group& gr : pre_groups)
       if ((r = strassen_pre_multi(d_pre + gr.begin, gr.count, gr.max_elems, s)) != GF2_OK) return r;
-    if (!expands.empty() && (r = m4rm_expand_list(d_expands, (int)expands.size(), expand_rows, s)) != GF2_OK)
+    if (!expands.empty() && (r = m4rm_expand_list(d_expands, (int)expands.size(), expand_dwords, s)) != GF2_OK)
       return r;
     {
       TraceScope tr(GF2_TRACE_BATCH, n_items, work, s);
@@ -1160,7 +1278,7 @@ gf2_status build_batch_plan(const gf2_problem* probs, int64_t count, BatchPlanIm
   if ((r = upload((void**)&P.d_fills, P.fills.data(), P.fills.size() * sizeof(OView))) != GF2_OK) return r;
   if ((r = upload((void**)&P.d_pre, P.pre.data(), P.pre.size() * sizeof(PreOp))) != GF2_OK) return r;
   if ((r = upload((void**)&P.d_post, P.post.data(), P.post.size() * sizeof(PostOp))) != GF2_OK) return r;
-  for (const ExpandOp& o : P.expands) P.expand_rows = std::max<int64_t>(P.expand_rows, o.m);
+  for (const ExpandOp& o : P.expands) P.expand_dwords = std::max<int64_t>(P.expand_dwords, (int64_t)o.m * 2 * o.ldx);
   if ((r = upload((void**)&P.d_expands, P.expands.data(), P.expands.size() * sizeof(ExpandOp))) != GF2_OK) return r;
   return GF2_OK;
 }

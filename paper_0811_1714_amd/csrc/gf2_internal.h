@@ -107,7 +107,7 @@ struct ExpandOp {
 };
 int64_t m4rm_expanded_ld(int64_t k, int kappa);
 gf2_status m4rm_expand(const ExpandOp* ops, int n, hipStream_t s);                          // host array
-gf2_status m4rm_expand_list(const ExpandOp* dev_ops, int n, int64_t max_rows, hipStream_t s);  // device array
+gf2_status m4rm_expand_list(const ExpandOp* dev_ops, int n, int64_t max_dwords, hipStream_t s);  // device array
 // One queue item of the persistent batch kernel: a C tile of descriptor ``desc``; ``variant``
 // holds the tile variant in bits 0-7 and the table width above.
 struct BatchItem {
@@ -164,6 +164,8 @@ struct OView {
   uint64_t tail;       // mask for word wds-1 (padding bits written 0 or left unchanged)
 };
 gf2_status fill_zero(const OView& o, hipStream_t s);
+// o := a XOR b over o's region (o may be a or b); traced as ``trace_kind``.
+gf2_status xor2(const OView& o, const QView& a, const QView& b, int trace_kind, hipStream_t s);
 // Strassen-Winograd passes of one recursion node (``depth`` 0 = the root), Algorithm 4.
 // Pre-additions: from the quadrants NW, NE, SW, SE of A (kind 0) produce S0..S3, of B
 // (kind 1) T0..T3, over R x Wd words.  Post-additions: from P0..P6 (ld ldp) write the

@@ -296,12 +296,21 @@ __device__ __forceinline__ void m4rm_tile_any(const MulDesc& d, int tm, int tn, 
 // banks 0-31, table 1 in banks 32-63) instead of contending for one half.
 constexpr int T2_WORDS = 16;                // 1024 columns per tile
 
+// B rows are loaded D phases ahead of the build that uses them (a ring of D register sets,
+// indexed by the phase modulo D, which the unrolled code knows at compile time).  Measured in
+// the persistent batch kernel: two phases ahead helps the four-table tiles of up to 1024 rows
+// (2-6% per product), while the two-table tiles, and any tile at four phases ahead, lose more
+// to the extra registers (saved and restored around each tile) than the shorter wait gains.
+template <int S, int TABLES>
+constexpr int prefetch_depth() { return TABLES == 4 && S <= 4 ? 2 : 1; }
+
 template <int WAVES, int S, int KAPPA = KB>
 struct Tile2 {
   static constexpr int RW = 8 * S;          // rows per wave: eight per lookup instruction
   static constexpr int BM = WAVES * RW;
   static constexpr int HIB = KAPPA - wave_bits<WAVES>();
   static constexpr int PR = 2 * KAPPA;      // rows of B per phase
+  static constexpr int D = prefetch_depth<S, 2>();   // B prefetch depth in phases (divides 8)
 };
 
 __device__ __forceinline__ uint4 xor3v(uint4 a, uint4 b, uint4 c) {
@@ -312,6 +321,7 @@ __device__ __forceinline__ uint4 xor3v(uint4 a, uint4 b, uint4 c) {
 template <int WAVES, int S, int INFL, int KAPPA, bool EDGE>
 __device__ __forceinline__ void m4rm2_tile(const MulDesc& d, int tm, int tn, char* tab) {
   using T = Tile2<WAVES, S, KAPPA>;
+  constexpr int D = T::D;
   const int tid = threadIdx.x;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int L = tid & 63, g8 = L >> 3, l8 = L & 7;
@@ -356,8 +366,8 @@ __device__ __forceinline__ void m4rm2_tile(const MulDesc& d, int tm, int tn, cha
 #pragma unroll
     for (int s = 0; s < S; ++s) dst[s] = bload1(ra, (8 * s + g8) * lda_b + 16 * c + 4 * (l8 & 3));
   };
-  StripeRows<KAPPA> sr;
-  auto fetch = [&](int p) {
+  StripeRows<KAPPA> ring[D];
+  auto fetch = [&](int p, StripeRows<KAPPA>& sr) {
     const int64_t kp = (int64_t)p * T::PR;
     const int rows = (int)imin64(d.k - kp, T::PR);
     const __amdgpu_buffer_rsrc_t rb = make_rsrc(d.B + kp * d.ldb + c0, (int64_t)(rows - 1) * ldb_b + 8 * Wt);
@@ -372,8 +382,9 @@ __device__ __forceinline__ void m4rm2_tile(const MulDesc& d, int tm, int tn, cha
   if (nphases > 0) {
     if constexpr (kChunked) load_chunk(0, ax);
     else load_a(0, ax);
-    fetch(0);
-    build_table<WAVES, KAPPA>(tab, 0, w, L, sr);
+#pragma unroll
+    for (int i = 0; i < D; ++i) fetch(i, ring[i]);        // phases 0 .. D-1
+    build_table<WAVES, KAPPA>(tab, 0, w, L, ring[0]);
   }
   __syncthreads();
 
@@ -383,7 +394,7 @@ __device__ __forceinline__ void m4rm2_tile(const MulDesc& d, int tm, int tn, cha
   // stay inside the tile's rows (or past the range, reading zero), and the data is never
   // used.  Keeping branches away from the loads lets the compiler wait for exactly the loads
   // each step needs.
-  auto lookups = [&](int p, uint32_t s0sel, uint32_t s1sel, auto dword) {
+  auto lookups = [&](int p, uint32_t s0sel, uint32_t s1sel, auto dword, const StripeRows<KAPPA>& next_rows) {
     const uint32_t buf = (uint32_t)(p & 1) << 16;
 #pragma unroll
     for (int s0 = 0; s0 < S; s0 += INFL) {
@@ -398,16 +409,18 @@ __device__ __forceinline__ void m4rm2_tile(const MulDesc& d, int tm, int tn, cha
       for (int s = s0; s < s0 + INFL && s < S; ++s)
         asm volatile("" : "+v"(acc[s].x), "+v"(acc[s].y), "+v"(acc[s].z), "+v"(acc[s].w));
     }
-    if (p + 1 < nphases) build_table<WAVES, KAPPA>(tab, (p & 1) ^ 1, w, L, sr);
+    if (p + 1 < nphases) build_table<WAVES, KAPPA>(tab, (p & 1) ^ 1, w, L, next_rows);
     __syncthreads();
   };
-  // Phase p = 8c + 2jj + U of chunk c (jj, U compile-time).
+  // Phase p = 8c + 2jj + U of chunk c (jj, U compile-time): its B rows leave ring slot p mod D,
+  // which then receives phase p + D's.
   auto phase = [&](int p, auto JJ, auto U, const uint32_t (&cur)[S], uint32_t (&nxt)[S]) {
-    constexpr int jj = decltype(JJ)::value, u = decltype(U)::value;
-    fetch(p + 1);
+    constexpr int jj = decltype(JJ)::value, u = decltype(U)::value, slot = (2 * jj + u) % D;
+    fetch(p + D, ring[slot]);
     if constexpr (jj == 0 && u == 0) load_chunk((p >> 3) + 1, nxt);
     lookups(p, u ? asel10 : asel00, u ? asel11 : asel01,
-            [&](int s) { return (uint32_t)__builtin_amdgcn_mov_dpp((int)cur[s], jj * 0x55, 0xf, 0xf, true); });
+            [&](int s) { return (uint32_t)__builtin_amdgcn_mov_dpp((int)cur[s], jj * 0x55, 0xf, 0xf, true); },
+            ring[(slot + 1) % D]);
   };
   using I0 = std::integral_constant<int, 0>;
   using I1 = std::integral_constant<int, 1>;
@@ -426,13 +439,20 @@ __device__ __forceinline__ void m4rm2_tile(const MulDesc& d, int tm, int tn, cha
   };
   // The one to seven phases of a last, partial chunk: the dword comes from the quad's lane
   // jj through ds_bpermute (jj known only at run time); speed does not matter here.
+  // Unrolled by D, so that each phase's ring slot is known at compile time.
   auto part = [&](int c, const uint32_t (&cur)[S]) {
-    for (int p = 8 * c; p < nphases; ++p) {
-      fetch(p + 1);
-      const int jj = (p >> 1) & 3, u = p & 1;
-      const int src = ((L & ~3) | jj) * 4;
-      lookups(p, u ? asel10 : asel00, u ? asel11 : asel01,
-              [&](int s) { return (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)cur[s]); });
+    for (int p0 = 8 * c; p0 < nphases; p0 += D) {
+#pragma unroll
+      for (int i = 0; i < D; ++i) {
+        const int p = p0 + i;
+        if (p < nphases) {
+          fetch(p + D, ring[i]);
+          const int jj = (p >> 1) & 3, u = p & 1;
+          const int src = ((L & ~3) | jj) * 4;
+          lookups(p, u ? asel10 : asel00, u ? asel11 : asel01,
+                  [&](int s) { return (uint32_t)__builtin_amdgcn_ds_bpermute(src, (int)cur[s]); }, ring[(i + 1) % D]);
+        }
+      }
     }
   };
   if constexpr (kChunked) {
@@ -457,11 +477,12 @@ __device__ __forceinline__ void m4rm2_tile(const MulDesc& d, int tm, int tn, cha
       load_a(gd + 1, nxt);
 #pragma unroll
       for (int s = 0; s < S; ++s) cur[s] = __builtin_amdgcn_perm(cur[s], cur[s], swp);
-      fetch(p0 + 1);
-      lookups(p0, sel00, sel01, [&](int s) { return cur[s]; });
+      static_assert(D == 1, "tiles of more than eight slots fetch one phase ahead");
+      fetch(p0 + 1, ring[0]);
+      lookups(p0, sel00, sel01, [&](int s) { return cur[s]; }, ring[0]);
       if (p0 + 1 < nphases) {
-        fetch(p0 + 2);
-        lookups(p0 + 1, sel10, sel11, [&](int s) { return cur[s]; });
+        fetch(p0 + 2, ring[0]);
+        lookups(p0 + 1, sel10, sel11, [&](int s) { return cur[s]; }, ring[0]);
       }
     };
     const int ngroups = (nphases + 1) >> 1;
@@ -516,11 +537,15 @@ struct Tile8 {
   static constexpr int BM = WAVES * RW;
   static constexpr int HIB = KAPPA - wave_bits<WAVES>();
   static constexpr int PR = 8 * KAPPA;      // rows of B per phase
+  // Loads run DA phases ahead (A indices and B rows), DA = 2 on the short tiles: a ring of NA
+  // sets of A registers and DA sets of B rows, both indexed by the phase modulo 4.
+  static constexpr int DA = S <= 2 ? 2 : 1, NA = 2 * DA;
 };
 
 template <int WAVES, int S, int KAPPA, bool EDGE>
 __device__ __forceinline__ void m4rm8_tile(const MulDesc& d, int tm, int tn, char* tab) {
   using T = Tile8<WAVES, S, KAPPA>;
+  constexpr int DA = T::DA, NA = T::NA;
   const int tid = threadIdx.x;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int L = tid & 63, r32 = L >> 1, half = L & 1;
@@ -553,13 +578,13 @@ __device__ __forceinline__ void m4rm8_tile(const MulDesc& d, int tm, int tn, cha
   uint4 acc[S];
 #pragma unroll
   for (int s = 0; s < S; ++s) acc[s] = make_uint4(0, 0, 0, 0);
-  uint2 ax[S], ay[S];
+  uint2 areg[NA][S];
   auto load_a = [&](int p, uint2 (&dst)[S]) {
 #pragma unroll
     for (int s = 0; s < S; ++s) dst[s] = bload2(ra, (32 * s + r32) * lda_b + 8 * p);
   };
-  StripeRows<KAPPA> sr;
-  auto fetch = [&](int p) {
+  StripeRows<KAPPA> ring[DA];
+  auto fetch = [&](int p, StripeRows<KAPPA>& sr) {
     const int64_t kp = (int64_t)p * T::PR;
     const int rows = (int)imin64(d.k - kp, T::PR);
     const __amdgpu_buffer_rsrc_t rb = make_rsrc(d.B + kp * d.ldb + c0, (int64_t)(rows - 1) * ldb_b + 8 * Wt);
@@ -567,9 +592,12 @@ __device__ __forceinline__ void m4rm8_tile(const MulDesc& d, int tm, int tn, cha
     for (int b = 0; b < KAPPA; ++b) sr.r[b] = bload1(rb, bo[b]);
   };
   if (nphases > 0) {
-    load_a(0, ax);
-    fetch(0);
-    build_table<WAVES, KAPPA>(tab, 0, w, L, sr);
+#pragma unroll
+    for (int i = 0; i < DA; ++i) {                        // phases 0 .. DA-1
+      load_a(i, areg[i]);
+      fetch(i, ring[i]);
+    }
+    build_table<WAVES, KAPPA>(tab, 0, w, L, ring[0]);
   }
   __syncthreads();
 
@@ -577,9 +605,11 @@ __device__ __forceinline__ void m4rm8_tile(const MulDesc& d, int tm, int tn, cha
   // unused stride-gap words, with no branch), and the byte permutation is pinned after the
   // barrier that ends the previous phase (an empty asm on each qword): hoisted above it, it
   // would wait there for loads that have only just been issued.
-  auto phase = [&](int p, uint2 (&cur)[S], uint2 (&nxt)[S]) {
-    fetch(p + 1);
-    load_a(p + 1, nxt);
+  auto phase = [&](int p, auto I) {
+    constexpr int i = decltype(I)::value;                 // p mod 4
+    uint2 (&cur)[S] = areg[i % NA];
+    fetch(p + DA, ring[i % DA]);
+    load_a(p + DA, areg[(i + DA) % NA]);
     const uint32_t lb = cb | ((uint32_t)(p & 1) << 16);
 #pragma unroll
     for (int s = 0; s < S; ++s) {
@@ -604,15 +634,23 @@ __device__ __forceinline__ void m4rm8_tile(const MulDesc& d, int tm, int tn, cha
         asm volatile("" : "+v"(acc[s].x), "+v"(acc[s].y), "+v"(acc[s].z), "+v"(acc[s].w));
       }
     }
-    if (p + 1 < nphases) build_table<WAVES, KAPPA>(tab, (p & 1) ^ 1, w, L, sr);
+    if (p + 1 < nphases) build_table<WAVES, KAPPA>(tab, (p & 1) ^ 1, w, L, ring[(i + 1) % DA]);
     __syncthreads();
   };
+  constexpr std::integral_constant<int, 0> I0{};
+  constexpr std::integral_constant<int, 1> I1{};
+  constexpr std::integral_constant<int, 2> I2{};
+  constexpr std::integral_constant<int, 3> I3{};
   int p = 0;
-  for (; p + 1 < nphases; p += 2) {
-    phase(p, ax, ay);
-    phase(p + 1, ay, ax);
+  for (; p + 3 < nphases; p += 4) {
+    phase(p, I0);
+    phase(p + 1, I1);
+    phase(p + 2, I2);
+    phase(p + 3, I3);
   }
-  if (p < nphases) phase(p, ax, ay);
+  if (p < nphases) phase(p, I0);
+  if (p + 1 < nphases) phase(p + 1, I1);
+  if (p + 2 < nphases) phase(p + 2, I2);
 
   const uint64_t tail = (d.n & 63) ? ((1ull << (d.n & 63)) - 1) : ~0ull;
   const uint64_t m0 = (EDGE && lw == Wt - 1) ? tail : ~0ull;
@@ -662,11 +700,13 @@ struct Tile4 {
   static constexpr int BM = WAVES * RW;
   static constexpr int HIB = KAPPA - wave_bits<WAVES>();
   static constexpr int PR = 4 * KAPPA;      // rows of B per phase
+  static constexpr int D = prefetch_depth<S, 4>();   // B prefetch depth in phases (divides 4)
 };
 
 template <int WAVES, int S, int KAPPA, bool EDGE>
 __device__ __forceinline__ void m4rm4_tile(const MulDesc& d, int tm, int tn, char* tab) {
   using T = Tile4<WAVES, S, KAPPA>;
+  constexpr int D = T::D;
   const int tid = threadIdx.x;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int L = tid & 63, r16 = L >> 2, qtr = L & 3;
@@ -709,7 +749,7 @@ __device__ __forceinline__ void m4rm4_tile(const MulDesc& d, int tm, int tn, cha
 #pragma unroll
     for (int s = 0; s < S; ++s) dst[s] = bload1(ra, (16 * s + r16) * lda_b + 16 * c + 4 * qtr);
   };
-  StripeRows<KAPPA> sr;
+  StripeRows<KAPPA> ring[D];
   // Ranges fit 31 bits: at most 31 rows of at most 2^24 bytes plus one row's valid bytes.
   const int wt_b = 8 * (int)Wt;
   // Phases are fetched in order, so the row pointer and the rows left advance by one phase
@@ -717,8 +757,8 @@ __device__ __forceinline__ void m4rm4_tile(const MulDesc& d, int tm, int tn, cha
   const char* bnext = reinterpret_cast<const char*>(d.B + c0);
   const int64_t bstep = (int64_t)T::PR * ldb_b;
   int64_t kleft = d.k;
-  auto fetch = [&](int) {
-    const int rows = (int)imin64(kleft, T::PR);           // > -PR even past the last phase
+  auto fetch = [&](StripeRows<KAPPA>& sr) {
+    const int rows = (int)imin64(kleft, T::PR);           // > -PR * D even past the last phase
     const int last = (rows - 1) * ldb_b + wt_b;           // range from the phase's first row
     const char* rowp = bnext;                             // row kp + b, and its range
     int left = last;
@@ -734,19 +774,21 @@ __device__ __forceinline__ void m4rm4_tile(const MulDesc& d, int tm, int tn, cha
   };
   if (nphases > 0) {
     load_chunk(0, ax);
-    fetch(0);
-    build_table<WAVES, KAPPA>(tab, 0, w, L, sr);
+#pragma unroll
+    for (int i = 0; i < D; ++i) fetch(ring[i]);           // phases 0 .. D-1
+    build_table<WAVES, KAPPA>(tab, 0, w, L, ring[0]);
   }
   __syncthreads();
 
-  // Phase p = 4c + J of chunk c.  The next phase's B rows and, at J = 0, the next chunk of A
-  // are loaded unconditionally: past the end the B range is empty and the A offsets stay
-  // inside the tile's rows (or past the range, reading zero), and what they bring is never
-  // used.  Keeping branches away from the loads lets the compiler wait for exactly the loads
-  // each step needs; B is issued first so the table build waits for it alone.
+  // Phase p = 4c + J of chunk c.  The B rows of phase p + D (into the ring slot phase p's rows
+  // have just left) and, at J = 0, the next chunk of A are loaded unconditionally: past the end
+  // the B range is empty and the A offsets stay inside the tile's rows (or past the range,
+  // reading zero), and what they bring is never used.  Keeping branches away from the loads
+  // lets the compiler wait for exactly the loads each step needs; B is issued first so the
+  // table build waits for it alone.
   auto phase = [&](int p, auto J, uint32_t (&cur)[S], uint32_t (&nxt)[S]) {
     constexpr int j = decltype(J)::value;
-    fetch(p + 1);
+    fetch(ring[j % D]);
     if constexpr (j == 0) load_chunk((p >> 2) + 1, nxt);
     const uint32_t lb = cb | ((uint32_t)(p & 1) << 16);
     const uint32_t l0 = lb, l1 = lb ^ 64u, l2 = lb ^ 128u, l3 = lb ^ 192u;
@@ -764,7 +806,7 @@ __device__ __forceinline__ void m4rm4_tile(const MulDesc& d, int tm, int tn, cha
     // Lookups run at a raised wave priority and the table build at the normal one, so waves
     // still looking up are issued ahead of waves already building (about 1% at 32768^3).
     __builtin_amdgcn_s_setprio(0);
-    if (p + 1 < nphases) build_table<WAVES, KAPPA>(tab, (p & 1) ^ 1, w, L, sr);
+    if (p + 1 < nphases) build_table<WAVES, KAPPA>(tab, (p & 1) ^ 1, w, L, ring[(j + 1) % D]);
     __syncthreads();
     __builtin_amdgcn_s_setprio(2);
   };
@@ -977,11 +1019,13 @@ __device__ __forceinline__ void m4rm32_tile_any(const MulDesc& d, int tm, int tn
 template <int WAVES, int RW>
 struct PolicyT1 {
   static constexpr int BM = WAVES * RW, TW = TILE_WORDS, NT = WAVES * 64, PR = KB;
+  static constexpr int LDS_BYTES = 2 * TABLE_BYTES;
   __device__ __forceinline__ static void run(const MulDesc& d, int tm, int tn, char* tab) { m4rm_tile_any<WAVES, RW>(d, tm, tn, tab); }
 };
 template <int WAVES, int S, int INFL, int KAPPA = KB>
 struct PolicyT2 {
   static constexpr int BM = Tile2<WAVES, S, KAPPA>::BM, TW = T2_WORDS, NT = WAVES * 64, PR = 2 * KAPPA;
+  static constexpr int LDS_BYTES = 2 * TABLE_BYTES;
   __device__ __forceinline__ static void run(const MulDesc& d, int tm, int tn, char* tab) {
     m4rm2_tile_any<WAVES, S, INFL, KAPPA>(d, tm, tn, tab);
   }
@@ -989,17 +1033,70 @@ struct PolicyT2 {
 template <int WAVES, int RPT>
 struct PolicyT32 {
   static constexpr int BM = Tile32<WAVES, RPT>::BM, TW = 1, NT = WAVES * 64, PR = P32;
+  static constexpr int LDS_BYTES = 2 * TABLE_BYTES;
   __device__ __forceinline__ static void run(const MulDesc& d, int tm, int tn, char* tab) { m4rm32_tile_any<WAVES, RPT>(d, tm, tn, tab); }
 };
 template <int WAVES, int S, int KAPPA = KB>
 struct PolicyT4 {
   static constexpr int BM = Tile4<WAVES, S, KAPPA>::BM, TW = T4_WORDS, NT = WAVES * 64, PR = 4 * KAPPA;
+  static constexpr int LDS_BYTES = 2 * TABLE_BYTES;
   __device__ __forceinline__ static void run(const MulDesc& d, int tm, int tn, char* tab) { m4rm4_tile_any<WAVES, S, KAPPA>(d, tm, tn, tab); }
 };
 template <int WAVES, int S, int KAPPA = KB>
 struct PolicyT8 {
   static constexpr int BM = Tile8<WAVES, S, KAPPA>::BM, TW = T8_WORDS, NT = WAVES * 64, PR = 8 * KAPPA;
+  static constexpr int LDS_BYTES = 2 * TABLE_BYTES;
   __device__ __forceinline__ static void run(const MulDesc& d, int tm, int tn, char* tab) { m4rm8_tile_any<WAVES, S, KAPPA>(d, tm, tn, tab); }
+};
+
+// Algorithm 1 as it stands, without the row blocking of Algorithm 2 (the ablation's first arm):
+// for each 8-row stripe of B, ONE table of the 256 combinations of the stripe's rows serves every
+// row of A, and C is read and written in global memory once per stripe.  A workgroup owns one
+// 64-bit column of C over all m rows (so its table entries are single words): it builds the
+// stripe's table -- 32 groups of 8 entries, each group a Gray walk in which every entry after the
+// first costs one row addition -- then adds T[x_j] into C[j] for every row j.
+struct PolicyAlg1 {
+  static constexpr int BM = 1 << 30, TW = 1, NT = 256, PR = KB, LDS_BYTES = 256 * 8;
+  __device__ __forceinline__ static void run(const MulDesc& d, int, int tn, char* tabc) {
+    uint64_t* tab = reinterpret_cast<uint64_t*>(tabc);
+    const int tid = threadIdx.x;
+    const int64_t Wn = words(d.n);
+    const uint64_t tail = ((d.n & 63) && tn == Wn - 1) ? ((1ull << (d.n & 63)) - 1) : ~0ull;
+    gword* col = (gword*)(d.C + tn);
+    if (d.out == OUT_STORE)
+      for (int64_t r = tid; r < d.m; r += NT) col[r * d.ldc] = 0;
+    const int nstripes = (d.k + KB - 1) / KB;
+    const int grp = tid >> 3, low = tid & 7;                // entry group (index bits 3..7), lane in it
+    for (int p = 0; p < nstripes; ++p) {
+      const int64_t kp = (int64_t)p * KB;
+      if (low == 0) {
+        uint64_t rows[KB];
+#pragma unroll
+        for (int b = 0; b < KB; ++b) rows[b] = kp + b < d.k ? d.B[(kp + b) * d.ldb + tn] & tail : 0;
+        uint64_t v = 0;
+#pragma unroll
+        for (int b = 3; b < KB; ++b)
+          if ((grp >> (b - 3)) & 1) v ^= rows[b];
+        tab[grp << 3] = v;
+#pragma unroll
+        for (int i = 1; i < 8; ++i) {
+          v ^= rows[__builtin_ctz(i)];
+          tab[(grp << 3) | (i ^ (i >> 1))] = v;
+        }
+      }
+      __syncthreads();
+      for (int64_t r = tid; r < d.m; r += NT) {
+        const uint32_t x = reinterpret_cast<const uint8_t*>(d.A + r * d.lda)[p];
+        const uint64_t t = tab[x];
+        if (d.out == OUT_ATOMIC) {
+          if (t) atomicXor(reinterpret_cast<unsigned long long*>(d.C + r * d.ldc + tn), (unsigned long long)t);
+        } else {
+          col[r * d.ldc] ^= t;
+        }
+      }
+      __syncthreads();
+    }
+  }
 };
 
 // Up to kMaxGroup products in one launch, descriptors passed by value (no device
@@ -1007,7 +1104,7 @@ struct PolicyT8 {
 // the product i with tile_start[i] <= b < tile_start[i+1].
 template <class P>
 __global__ __launch_bounds__(P::NT) void m4rm_group(GroupArgs g) {
-  __shared__ uint4 tab[2 * TABLE_BYTES / 16];
+  __shared__ uint4 tab[P::LDS_BYTES / 16];
   const int b = blockIdx.x;
   const int t = b < g.remap_n ? xcd_remap(b, g.remap_n) : b;
   int i = 0;
@@ -1059,11 +1156,12 @@ using V17 = PolicyT4<16, 6>;      // t=4, BM 1536
 template <int K> using V18 = PolicyT4<16, 4, K>;     // t=4, BM 1024
 template <int K> using V19 = PolicyT4<16, 2, K>;     // t=4, BM 512
 template <int K> using V20 = PolicyT4<16, 1, K>;     // t=4, BM 256
+using V21 = PolicyAlg1;           // Algorithm 1: one table per stripe for all m rows, C in global memory
 const Variant kVariants[] = {variant8<V0>(), variantk<V1>(), variantk<V2>(), variantk<V3>(), variantk<V4>(),
                              variant8<V5>(), variant8<V6>(), variant8<V7>(), variant8<V8>(), variant8<V9>(),
                              variant8<V10>(), variant8<V11>(), variantk<V12>(), variantk<V13>(), variant8<V14>(),
                              variant8<V15>(), variant8<V16>(), variant8<V17>(), variantk<V18>(), variantk<V19>(),
-                             variantk<V20>()};
+                             variantk<V20>(), variant8<V21>()};
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
 // The persistent kernel's tables, at file scope so that the tile functions below address
@@ -1147,15 +1245,19 @@ __global__ void reset_counter(int* c) { *c = 0; }
 // index bits, row r's stripe j is selected by bits kappa*j .. kappa*j + kappa - 1 of A's row).
 // Byte j of row r of X holds that field (its bit 0 = column kappa*j); bits of A at or past k
 // read as zero and X's bytes past ceil(k / kappa), up to the row's ldx words, are written 0, so
-// the M4RM tiles read one index byte per lookup whatever the width.  One block per row at a
-// time, one dword of X per thread.
+// the M4RM tiles read one index byte per lookup whatever the width.  One dword of X per thread,
+// the op's dwords spread over all of the launch's threads (products of a batch are small, and
+// a block per row would leave most threads idle).
 __device__ __forceinline__ void expand_rows(const ExpandOp& o) {
   const int dws = (int)(2 * o.ldx);
   const int kw = (int)words(o.k);
-  for (int64_t r = blockIdx.x; r < o.m; r += gridDim.x) {
+  const int64_t total = (int64_t)o.m * dws;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e < 0xffffffffll ? (int64_t)((uint32_t)e / (uint32_t)dws) : e / dws;
+    const int j = (int)(e - r * dws);
     const uint64_t* row = o.A + r * o.lda;
     uint32_t* dst = reinterpret_cast<uint32_t*>(o.X + r * o.ldx);
-    for (int j = threadIdx.x; j < dws; j += blockDim.x) {
+    {
       uint32_t out = 0;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -1184,7 +1286,10 @@ __global__ __launch_bounds__(256) void expand_list(const ExpandOp* __restrict__ 
 
 const Variant& variant_of(int v) { return kVariants[(v < 0 || v >= kNumVariants) ? 0 : v]; }
 
-unsigned expand_grid_x(int64_t max_rows) { return (unsigned)std::max<int64_t>(1, std::min<int64_t>(max_rows, 1024)); }
+// Blocks per op: enough for the largest op's dwords (256 per block), at most 1024.
+unsigned expand_grid_x(int64_t max_dwords) {
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>((max_dwords + 255) / 256, 1024));
+}
 
 }  // namespace
 
@@ -1208,22 +1313,22 @@ gf2_status m4rm_expand(const ExpandOp* ops, int n, hipStream_t s) {
   for (int i = 0; i < n; i += kExpandOps) {
     ExpandArgs a;
     a.count = std::min(kExpandOps, n - i);
-    int64_t rows = 0;
+    int64_t dwords = 0;
     for (int j = 0; j < a.count; ++j) {
       a.op[j] = ops[i + j];
-      rows = std::max<int64_t>(rows, a.op[j].m);
+      dwords = std::max<int64_t>(dwords, (int64_t)a.op[j].m * 2 * a.op[j].ldx);
     }
-    hipLaunchKernelGGL(expand_group, dim3(expand_grid_x(rows), (unsigned)a.count), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(expand_group, dim3(expand_grid_x(dwords), (unsigned)a.count), dim3(256), 0, s, a);
     gf2_status st = hip_check(hipGetLastError(), "expand_group launch");
     if (st != GF2_OK) return st;
   }
   return GF2_OK;
 }
 
-gf2_status m4rm_expand_list(const ExpandOp* dev_ops, int n, int64_t max_rows, hipStream_t s) {
+gf2_status m4rm_expand_list(const ExpandOp* dev_ops, int n, int64_t max_dwords, hipStream_t s) {
   for (int i = 0; i < n; i += 65535) {   // grid y limit
     const int c = std::min(65535, n - i);
-    hipLaunchKernelGGL(expand_list, dim3(expand_grid_x(max_rows), (unsigned)c), dim3(256), 0, s, dev_ops + i);
+    hipLaunchKernelGGL(expand_list, dim3(expand_grid_x(max_dwords), (unsigned)c), dim3(256), 0, s, dev_ops + i);
     gf2_status st = hip_check(hipGetLastError(), "expand_list launch");
     if (st != GF2_OK) return st;
   }

@@ -8,20 +8,40 @@
 namespace gf2 {
 namespace {
 
-// The candidate list: M4RM tile heights (the persistent-kernel variants first), split-K
-// for tall-narrow work, one Strassen-Winograd level, the 1536-row tile, and the two
-// other base cases.  Index order is part of the ABI (schedule model outputs follow it).
+// The candidate list: every tile the persistent batch kernel runs (two-table tiles of 1024 to
+// 128 rows, four-table tiles of 1024 to 256, eight-table tiles of 1024 and 512) with 8-bit
+// tables, the short ones also with 7- to 5-bit tables (a product of few rows builds its tables
+// for few lookups), k-split and one-level Strassen-Winograd forms, then schedules that only run
+// as grouped launches (the tallest tiles, the int8 matrix core, the popcount kernel).  Index
+// order is part of the ABI (schedule model outputs follow it).
 const gf2_schedule kCandidates[] = {
-    {GF2_KERNEL_M4RM, 1, 0, 1},      // 0: t=2, 1024 rows
-    {GF2_KERNEL_M4RM, 2, 0, 1},      // 1: t=2, 512 rows
-    {GF2_KERNEL_M4RM, 3, 0, 1},      // 2: t=2, 256 rows
-    {GF2_KERNEL_M4RM, 4, 0, 1},      // 3: t=2, 128 rows
-    {GF2_KERNEL_M4RM, 2, 0, 4},      // 4: 512 rows, k in 4 slices
-    {GF2_KERNEL_M4RM, 3, 0, 16},     // 5: 256 rows, k in 16 slices
-    {GF2_KERNEL_M4RM, 1, 1024, 1},   // 6: Strassen-Winograd above 1024, 1024-row leaves
-    {GF2_KERNEL_M4RM, 0, 0, 1},      // 7: t=2, 1536 rows
-    {GF2_KERNEL_MFMA, 0, 0, 1},      // 8: int8 matrix core
-    {GF2_KERNEL_CUBIC, 0, 0, 1},     // 9: popcount
+    {GF2_KERNEL_M4RM, 1, 0, 1, 0, 8},      //  0: t=2, 1024 rows x 1024 columns
+    {GF2_KERNEL_M4RM, 2, 0, 1, 0, 8},      //  1: t=2, 512 rows
+    {GF2_KERNEL_M4RM, 3, 0, 1, 0, 8},      //  2: t=2, 256 rows
+    {GF2_KERNEL_M4RM, 4, 0, 1, 0, 8},      //  3: t=2, 128 rows
+    {GF2_KERNEL_M4RM, 18, 0, 1, 0, 8},     //  4: t=4, 1024 rows x 512 columns
+    {GF2_KERNEL_M4RM, 19, 0, 1, 0, 8},     //  5: t=4, 512 rows
+    {GF2_KERNEL_M4RM, 20, 0, 1, 0, 8},     //  6: t=4, 256 rows
+    {GF2_KERNEL_M4RM, 12, 0, 1, 0, 8},     //  7: t=8, 1024 rows x 256 columns
+    {GF2_KERNEL_M4RM, 13, 0, 1, 0, 8},     //  8: t=8, 512 rows
+    {GF2_KERNEL_M4RM, 4, 0, 1, 0, 7},      //  9: t=2, 128 rows, 7-bit tables
+    {GF2_KERNEL_M4RM, 4, 0, 1, 0, 6},      // 10: t=2, 128 rows, 6-bit tables
+    {GF2_KERNEL_M4RM, 4, 0, 1, 0, 5},      // 11: t=2, 128 rows, 5-bit tables
+    {GF2_KERNEL_M4RM, 3, 0, 1, 0, 7},      // 12: t=2, 256 rows, 7-bit tables
+    {GF2_KERNEL_M4RM, 3, 0, 1, 0, 6},      // 13: t=2, 256 rows, 6-bit tables
+    {GF2_KERNEL_M4RM, 20, 0, 1, 0, 7},     // 14: t=4, 256 rows, 7-bit tables
+    {GF2_KERNEL_M4RM, 20, 0, 1, 0, 6},     // 15: t=4, 256 rows, 6-bit tables
+    {GF2_KERNEL_M4RM, 13, 0, 1, 0, 7},     // 16: t=8, 512 rows, 7-bit tables
+    {GF2_KERNEL_M4RM, 13, 0, 1, 0, 6},     // 17: t=8, 512 rows, 6-bit tables
+    {GF2_KERNEL_M4RM, 2, 0, 4, 0, 8},      // 18: t=2, 512 rows, k in 4 slices
+    {GF2_KERNEL_M4RM, 3, 0, 16, 0, 8},     // 19: t=2, 256 rows, k in 16 slices
+    {GF2_KERNEL_M4RM, 19, 0, 4, 0, 8},     // 20: t=4, 512 rows, k in 4 slices
+    {GF2_KERNEL_M4RM, 1, 1024, 1, 0, 8},   // 21: Strassen-Winograd above 1024, t=2 1024-row leaves
+    {GF2_KERNEL_M4RM, 18, 1024, 1, 0, 8},  // 22: Strassen-Winograd above 1024, t=4 1024-row leaves
+    {GF2_KERNEL_M4RM, 0, 0, 1, 0, 8},      // 23: t=2, 1536 rows (grouped launch)
+    {GF2_KERNEL_M4RM, 16, 0, 1, 0, 8},     // 24: t=4, 2048 rows (grouped launch)
+    {GF2_KERNEL_MFMA, 0, 0, 1, 0, 8},      // 25: int8 matrix core
+    {GF2_KERNEL_CUBIC, 0, 0, 1, 0, 8},     // 26: popcount
 };
 constexpr int kNumCandidates = sizeof(kCandidates) / sizeof(kCandidates[0]);
 
@@ -30,19 +50,21 @@ constexpr int kNumCandidates = sizeof(kCandidates) / sizeof(kCandidates[0]);
 int num_candidates() { return kNumCandidates; }
 const gf2_schedule& candidate(int i) { return kCandidates[i]; }
 
-// The fixed heuristic (no tuning data): among the persistent-kernel M4RM tiles, the one
-// that minimises (tiles) x (16-row phases) x (rows per tile + the table build, counted
-// as 256 row lookups per phase) -- the paper's trade-off between block size and the
-// cost of regenerating the tables (Section 3.2), with LDS in place of cache.
+// The fixed heuristic (no tuning data): among the persistent-kernel tiles with 8-bit tables,
+// the one that minimises (tiles) x (barrier phases) x (tile rows + the table build, counted as
+// 256 rows) -- the paper's trade-off between block size and the cost of regenerating the
+// tables (Section 3.2), with LDS in place of cache.  Every tile family reads 256 B of tables
+// per row and phase and builds 64 KiB per phase; t tables per phase cover 8t rows of B and a
+// tile 2048/t columns wide.
 int fixed_candidate(int64_t m, int64_t k, int64_t n) {
   int best = 0;
   double best_cost = 0;
-  for (int c = 0; c <= 3; ++c) {
+  for (int c = 0; c <= 8; ++c) {
     const gf2_schedule& s = kCandidates[c];
-    const int64_t bm = m4rm_tile_rows(s.variant), tw = m4rm_tile_words(s.variant);
+    const int64_t bm = m4rm_tile_rows(s.variant), tw = m4rm_tile_words(s.variant), pr = m4rm_phase_rows(s.variant);
     const double tiles = (double)((m + bm - 1) / bm) * (double)((words(n) + tw - 1) / tw);
-    const double cost = tiles * (double)((k + 15) / 16) * (double)(bm + 256);
-    if (c == 0 || cost < best_cost) { best = c; best_cost = cost; }
+    const double cost = tiles * (double)((k + pr - 1) / pr) * (double)(bm + 256);
+    if (best_cost == 0 || cost < best_cost) { best = c; best_cost = cost; }
   }
   return best;
 }
@@ -105,18 +127,17 @@ gf2_status model_choose_batch(const std::vector<float>& feats_raw, const uint8_t
     for (int i = 0; i < 4; ++i)
       x[4 * b + i] = (float)((raw[i] - g_norm[i]) / (g_norm[4 + i] != 0 ? g_norm[4 + i] : 1.0f));
   }
-  // One allocation: X, Y, acts, allowed, out.
+  // One allocation: X, Y, acts, allowed (one byte per output, padded to 64), out.
   const int NO = 2 * kNumCandidates;   // batch outputs are the second half
-  const size_t fX = nb * 4, fY = nb * NO, fA = 3 * nb * 64;
-  const size_t bytes = (fX + fY + fA) * sizeof(float) + 64 + nb * sizeof(int32_t);
+  const size_t fX = nb * 4, fY = nb * NO, fA = 3 * nb * 64, mask_bytes = (NO + 63) & ~size_t(63);
+  const size_t bytes = (fX + fY + fA) * sizeof(float) + mask_bytes + nb * sizeof(int32_t);
   char* buf = nullptr;
-  static_assert(2 * kNumCandidates <= 64, "allowed mask area");
   if (hipMalloc(&buf, bytes) != hipSuccess) return set_error(GF2_ERR_ALLOC, "hipMalloc for model inference failed");
   float* dX = reinterpret_cast<float*>(buf);
   float* dY = dX + fX;
   float* dA = dY + fY;
   uint8_t* dAllowed = reinterpret_cast<uint8_t*>(dA + fA);
-  int32_t* dOut = reinterpret_cast<int32_t*>(dAllowed + 64);
+  int32_t* dOut = reinterpret_cast<int32_t*>(dAllowed + mask_bytes);
   std::vector<int32_t> host_out(nb);
   r = hip_check(hipMemcpy(dX, x.data(), fX * sizeof(float), hipMemcpyHostToDevice), "hipMemcpy");
   std::vector<uint8_t> mask(NO, 0);

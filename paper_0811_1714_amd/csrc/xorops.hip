@@ -125,6 +125,17 @@ __global__ void fill_zero_multi_kernel(const OView* __restrict__ ops) {
   }
 }
 
+// out := a XOR b over out's region; a and b read as zero past their rows and words (the
+// additions of Section 4's two-temporary schedule).  out may be a or b itself: each word is
+// read before it is written, by the same thread.
+__global__ void xor2_kernel(OView o, QView a, QView b) {
+  const int64_t total = o.rows * o.wds;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / o.wds, w = i - r * o.wds;
+    owrite(o, r, w, qload(a, r, w) ^ qload(b, r, w), OUT_STORE);
+  }
+}
+
 unsigned grid_for(int64_t total) {
   int64_t b = (total + kThreads - 1) / kThreads;
   const int64_t cap = 256 * 16;
@@ -138,6 +149,13 @@ gf2_status fill_zero(const OView& o, hipStream_t s) {
   TraceScope trace(GF2_TRACE_FILL, 1, 8.0 * o.rows * o.wds, s);
   hipLaunchKernelGGL(fill_zero_kernel, dim3(grid_for(o.rows * o.wds)), dim3(kThreads), 0, s, o);
   return hip_check(hipGetLastError(), "fill_zero launch");
+}
+
+gf2_status xor2(const OView& o, const QView& a, const QView& b, int trace_kind, hipStream_t s) {
+  if (o.rows <= 0 || o.wds <= 0) return GF2_OK;
+  TraceScope trace(trace_kind, 1, 24.0 * o.rows * o.wds, s);
+  hipLaunchKernelGGL(xor2_kernel, dim3(grid_for(o.rows * o.wds)), dim3(kThreads), 0, s, o, a, b);
+  return hip_check(hipGetLastError(), "xor2 launch");
 }
 
 // Multi-op launches: blockIdx.y selects the op; x blocks stride over its words.

@@ -109,12 +109,36 @@ def test_batch_validation_without_device():
 
 
 def test_schedule_struct_layout():
-    """gf2_schedule is six int32 fields (kernel, variant, cutoff, splitk, odd, kappa)."""
+    """gf2_schedule is seven int32 fields (kernel, variant, cutoff, splitk, odd, kappa, memory)."""
     import ctypes
     import paper_0811_1714_amd as g
-    assert ctypes.sizeof(g.Schedule) == 24
-    assert [f[0] for f in g.Schedule._fields_] == ["kernel", "variant", "cutoff", "splitk", "odd", "kappa"]
-    assert (g.ODD_PAD, g.ODD_PEEL) == (0, 1)
+    assert ctypes.sizeof(g.Schedule) == 28
+    assert [f[0] for f in g.Schedule._fields_] == ["kernel", "variant", "cutoff", "splitk", "odd", "kappa", "memory"]
+    assert (g.ODD_PAD, g.ODD_PEEL, g.MEM_FAST, g.MEM_LOW) == (0, 1, 0, 1)
+
+
+def test_two_temporary_workspace():
+    """Section 4's memory-efficient schedule at the top level keeps two temporaries, X (m/2 x
+    max(k, n)/2) and Y (k/2 x n/2), plus the breadth-first workspace of one of its products."""
+    import paper_0811_1714_amd as g
+    low = g.Schedule(g.KERNEL_M4RM, 1, 256, 1, 0, 0, g.MEM_LOW)
+    fast = g.Schedule(g.KERNEL_M4RM, 1, 256, 1, 0, 0, g.MEM_FAST)
+    # 1024^3: X, Y 512 x 8 words each; a 512^3 product one level down: 15 quadrants of 256 x 4 words.
+    assert g.workspace_bytes(1024, 1024, 1024, low) == (2 * 512 * 8 + 15 * 256 * 4) * 8
+    assert g.workspace_bytes(1024, 1024, 1024, fast) == (15 * 512 * 8 + 7 * 15 * 256 * 4) * 8
+    # 32768^3 over 8192-row leaves: 1320 MiB breadth-first, 184 MiB with two temporaries.
+    big_low = g.Schedule(g.KERNEL_M4RM, 16, 8192, 1, 0, 0, g.MEM_LOW)
+    big_fast = g.Schedule(g.KERNEL_M4RM, 16, 8192, 1, 0, 0, g.MEM_FAST)
+    assert g.workspace_bytes(32768, 32768, 32768, big_fast) == 1320 << 20
+    assert g.workspace_bytes(32768, 32768, 32768, big_low) == 184 << 20
+    # Odd rows: the two-temporary form does not apply, the figure is the breadth-first one.
+    assert g.workspace_bytes(1025, 1024, 1024, low) == g.workspace_bytes(1025, 1024, 1024, fast)
+    try:
+        g.resolve_schedule(100, 100, 100, g.Schedule(g.KERNEL_M4RM, 1, 0, 1, 0, 0, 2))
+    except g.GF2Error as e:
+        assert e.status == 1
+    else:
+        raise AssertionError("workspace plan 2 accepted")
 
 
 def test_table_width_validation_and_workspace():

@@ -20,9 +20,9 @@ def g():
     return g
 
 
-def M4RM(variant=0, cutoff=0, splitk=1, odd=0, kappa=0):
+def M4RM(variant=0, cutoff=0, splitk=1, odd=0, kappa=0, memory=0):
     import paper_0811_1714_amd as g
-    return g.Schedule(g.KERNEL_M4RM, variant, cutoff, splitk, odd, kappa)
+    return g.Schedule(g.KERNEL_M4RM, variant, cutoff, splitk, odd, kappa, memory)
 
 
 # Tiles that offer tables narrower than 8 bits (Section 3.1's k): every tile of at most 1024 rows.
@@ -73,6 +73,30 @@ def test_narrow_tables_with_recursion_split_and_peeling(g, shape, sched):
     wide = run_and_check(g, m, k, n, schedule=M4RM(v, cutoff, sk, odd), seed=21, lda_pad=2, ldc_pad=1)
     assert np.array_equal(base, wide)
     run_and_check(g, m, k, n, schedule=M4RM(v, cutoff, sk, odd, kappa), accumulate=True, seed=22, ldb_pad=1)
+
+
+@pytest.mark.parametrize("m,k,n,cutoff,variant", [
+    (2048, 2048, 2048, 512, 1),      # two-temporary top level, one breadth-first level below
+    (1024, 1500, 1024, 256, 3),      # k halves unequal (k1 < k0): S3, T3 and P1..P3 use k1
+    (1536, 777, 2560, 300, 18),      # two levels below the top
+    (3000, 3000, 3000, 1024, 16),    # four-table leaves
+])
+def test_two_temporary_schedule_same_bits(g, m, k, n, cutoff, variant):
+    """Section 4's memory-efficient schedule (two temporaries at the top level, products written
+    straight into C's quadrants) gives the breadth-first schedule's bits."""
+    print(f"two-temporary {(m, k, n)} cutoff {cutoff} variant {variant}", flush=True)
+    low = run_and_check(g, m, k, n, schedule=M4RM(variant, cutoff, memory=1), seed=31, lda_pad=1, ldb_pad=2,
+                        ldc_pad=1)
+    fast = run_and_check(g, m, k, n, schedule=M4RM(variant, cutoff), seed=31, lda_pad=1, ldb_pad=2, ldc_pad=1)
+    assert np.array_equal(low, fast)
+
+
+def test_two_temporary_schedule_falls_back(g):
+    """Where the two-temporary form does not apply (odd rows, columns not a multiple of 128,
+    accumulation) the call runs breadth-first, with the same bits."""
+    for (m, k, n, acc) in [(1025, 1024, 1024, False), (1024, 1024, 1000, False), (1024, 1024, 1024, True)]:
+        print(f"two-temporary fallback {(m, k, n)} accumulate {acc}", flush=True)
+        run_and_check(g, m, k, n, schedule=M4RM(1, 256, memory=1), accumulate=acc, seed=32)
 
 
 @pytest.mark.parametrize("m,k,n", [(100, 300, 70), (513, 2048, 2100), (64, 65, 4096)])

@@ -1,6 +1,7 @@
 """Seeded random cross-checks of the whole product path against the CPU oracle: random
 shapes (log-uniform in [8, 5000], one in five in [1000, 6000]), densities, strides and modes under random schedules
-(any base kernel and tile variant, Strassen-Winograd cutoff, odd-size rule, k split and M4RM table width).
+(any base kernel and tile variant, Strassen-Winograd cutoff, odd-size rule, k split, M4RM table width and
+workspace plan).
 Every result must be bit-exact whatever the schedule."""
 import numpy as np
 import pytest
@@ -33,7 +34,9 @@ def random_case(rng, g):
              lda_pad=int(rng.integers(3)), ldb_pad=int(rng.integers(3)), ldc_pad=int(rng.integers(3)))
     # Table width: 8, or 4..7 on the tiles that offer narrow tables.
     kappa = int(rng.choice([0, 4, 5, 6, 7])) if kernel == g.KERNEL_M4RM and variant in NARROW else 0
-    c["schedule"] = (kernel, variant, cutoff, splitk, odd, kappa)
+    # Workspace plan: breadth-first, or two temporaries at the top level (where it applies).
+    memory = int(rng.integers(2)) if cutoff else 0
+    c["schedule"] = (kernel, variant, cutoff, splitk, odd, kappa, memory)
     return c
 
 
