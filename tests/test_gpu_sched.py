@@ -101,7 +101,7 @@ def test_autotune_and_policies_keep_bits(g):
 
 
 def test_trained_model_gain_over_fixed_heuristic_on_fresh_shapes(g):
-    """What the trained network gains over the method without it.  On 32 shapes it never
+    """What the trained network gains over the method without it.  On 128 shapes it never
     saw (the batch workload's shape law, a seed disjoint from training and held-out data),
     every candidate the persistent batch kernel can run is timed per product inside a batch
     of copies (exhaustive autotune, the yardstick for regret).  The model's pick (batch head)
@@ -111,8 +111,8 @@ def test_trained_model_gain_over_fixed_heuristic_on_fresh_shapes(g):
     import synth
     if not os.path.exists(g.DEFAULT_MODEL):
         pytest.skip("no trained model")
-    dims = synth.log_uniform_dims(77, 5, 32, 64, 4096)
-    dens = synth.log_uniform_p(77, 1005, 32, 0.01, 0.5)
+    dims = synth.log_uniform_dims(77, 5, 128, 64, 4096)
+    dens = synth.log_uniform_p(77, 1005, 128, 0.01, 0.5)
     allowed = np.array([g.batch_candidate(i) for i in range(g.num_candidates())])
     r_model, r_fixed = [], []
     try:
