@@ -170,7 +170,7 @@ def mul_ptr(C, ldc, A, lda, B, ldb, m, k, n, *, accumulate=False, schedule=None,
 
 NOALLOC_SCRATCH_BYTES = 64 << 20   # GF2_NOALLOC_SCRATCH_BYTES
 # M4RM tile variants the persistent batch kernel runs (the candidates a batch may use).
-BATCH_VARIANTS = (1, 2, 3, 4, 12, 13, 18, 19, 20)
+BATCH_VARIANTS = (1, 2, 3, 4, 11, 12, 13, 16, 17, 18, 19, 20)
 
 
 def batch_candidate(index):

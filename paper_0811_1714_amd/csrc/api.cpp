@@ -707,6 +707,22 @@ size_t workspace_words(int64_t m, int64_t k, int64_t n, const gf2_schedule& s, b
   return fast_workspace_words(m, k, n, s);
 }
 
+// True when the plan is a node with seven children that are nodes of leaves (two levels), no
+// peeling fix-ups, and every split exact: m a multiple of 4, k and n multiples of 256, so that
+// every operand of both levels is a 4 x 4 block of equal sub-quadrants.  Plans are built depth
+// first, so the pre-additions are [node A, node B, child 0 A, child 0 B, ...] and the
+// post-additions [child 0, ..., child 6, node].
+bool two_level_exact(const StrassenPlan& pl, int64_t m, int64_t k, int64_t n) {
+  if (!pl.kfix.empty() || !pl.fix.empty() || pl.pre.size() != 16 || pl.post.size() != 8 || pl.leaves.size() != 49)
+    return false;
+  if (m % 4 || k % 256 || n % 256) return false;
+  for (size_t i = 0; i < pl.pre.size(); ++i)
+    if (pl.pre[i].depth != (i < 2 ? 0 : 1) || pl.pre[i].kind != (int)(i & 1)) return false;
+  for (size_t i = 0; i < pl.post.size(); ++i)
+    if (pl.post[i].depth != (i < 7 ? 1 : 0)) return false;
+  return true;
+}
+
 // Launches of one product whose workspace (Strassen temporaries, then the base kernel's
 // scratch; ``workspace_words`` of them) starts at ``ws``.  Enqueues kernels only.
 gf2_status execute_in(uint64_t* C, int64_t ldc, const uint64_t* A, int64_t lda, const uint64_t* B, int64_t ldb,
@@ -716,6 +732,53 @@ gf2_status execute_in(uint64_t* C, int64_t ldc, const uint64_t* A, int64_t lda, 
   ProductPlan pp;
   plan_product(pp, ws, C, ldc, A, lda, B, ldb, m, k, n, accumulate, s);
   uint64_t* scratch = ws ? ws + pp.st.ws_words + pp.x_words : nullptr;
+  if (!pp.st.leaves.empty() && two_level_exact(pp.st, m, k, n)) {
+    // A node and its seven children with every split exact: both levels' pre-additions in one
+    // pass, the leaves, both levels' post-additions in one pass.
+    const PreOp& ra = pp.st.pre[0];
+    const PreOp& rb = pp.st.pre[1];
+    Pre2Op pa{}, pb{};
+    pa.kind = 0;
+    pa.in = ra.in[0].p;
+    pa.ldi = ra.in[0].ld;
+    pa.R4 = m / 4;
+    pa.W4 = words(k) / 4;
+    pa.ldn = ra.ldo;
+    pb.kind = 1;
+    pb.in = rb.in[0].p;
+    pb.ldi = rb.in[0].ld;
+    pb.R4 = k / 4;
+    pb.W4 = words(n) / 4;
+    pb.ldn = rb.ldo;
+    for (int t = 0; t < 4; ++t) {
+      pa.node[t] = ra.out[t];
+      pb.node[t] = rb.out[t];
+    }
+    for (int c = 0; c < 7; ++c) {
+      const PreOp& ca = pp.st.pre[2 + 2 * c];
+      const PreOp& cb = pp.st.pre[3 + 2 * c];
+      for (int t = 0; t < 4; ++t) {
+        pa.child[c][t] = ca.out[t];
+        pb.child[c][t] = cb.out[t];
+      }
+      pa.ldc = ca.ldo;
+      pb.ldc = cb.ldo;
+    }
+    if ((r = strassen_pre2(pa, pb, st)) != GF2_OK) return r;
+    if ((r = m4rm_expand(pp.expands.data(), (int)pp.expands.size(), st)) != GF2_OK) return r;
+    if ((r = run_leaves(s, pp.st.leaves, scratch, st)) != GF2_OK) return r;
+    const PostOp& root = pp.st.post[7];
+    Post2Op po{};
+    po.mode = root.mode;
+    for (int c = 0; c < 7; ++c)
+      for (int j = 0; j < 7; ++j) po.P[c][j] = pp.st.post[c].P[j];
+    po.ldp = pp.st.post[0].ldp;
+    po.C = root.c[0].p;
+    po.ldc = root.c[0].ld;
+    po.R4 = m / 4;
+    po.W4 = words(n) / 4;
+    return strassen_post2(po, st);
+  }
   if (!pp.st.leaves.empty()) {
     // Passes of one recursion depth are independent: pre-additions run depth by depth from
     // the root down, post-additions from the deepest level up, each depth in few launches.

@@ -184,6 +184,31 @@ struct PostOp {
   int64_t ldp;
   OView c[4];          // C_NW, C_NE, C_SW, C_SE
 };
+// Two recursion levels in one pass (a node and its seven children, every split exact: all
+// operands are 4 x 4 blocks of R4 x W4-word sub-quadrants).  Pre: from ``in`` (A for kind 0,
+// B for kind 1) the node's four S (T) into ``node`` and child c's four S' (T') into child[c].
+struct Pre2Op {
+  int32_t kind;
+  const uint64_t* in;
+  int64_t ldi, R4, W4;
+  uint64_t* node[4];
+  int64_t ldn;
+  uint64_t* child[7][4];
+  int64_t ldc;
+};
+struct Pre2Args {
+  Pre2Op op[2];
+};
+// Post: from child c's leaf products P[c][0..6] (ld ldp) the node's C (mode OUT_STORE or OUT_XOR).
+struct Post2Op {
+  int32_t mode;
+  const uint64_t* P[7][7];
+  int64_t ldp;
+  uint64_t* C;
+  int64_t ldc, R4, W4;
+};
+gf2_status strassen_pre2(const Pre2Op& a_side, const Pre2Op& b_side, hipStream_t s);
+gf2_status strassen_post2(const Post2Op& a, hipStream_t s);
 // Many independent ops in one launch (device arrays); max_elems = largest op's word count.
 gf2_status fill_zero_multi(const OView* dev_ops, int n, int64_t max_elems, hipStream_t s);
 gf2_status strassen_pre_multi(const PreOp* dev_ops, int n, int64_t max_elems, hipStream_t s);

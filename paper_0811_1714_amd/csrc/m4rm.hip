@@ -1209,9 +1209,9 @@ __device__ __forceinline__ void run_kappa(int kappa, const MulDesc& d, int tm, i
 
 // Persistent batch kernel: one workgroup per compute unit pulls tile items from an
 // atomic queue (ordered longest first) until it runs dry; every item names its product,
-// one of the 16-wave variants of at most 1024 rows (two, four or eight tables per phase)
-// and its table width (variant | width << 8).  Each tile ends on a barrier, so LDS is free
-// for the next item.
+// one of the 16-wave variants (two tables per phase up to 1024 rows, four or eight up to
+// 2048) and its table width (variant | width << 8; the tiles of more than 1024 rows only
+// take 8).  Each tile ends on a barrier, so LDS is free for the next item.
 __global__ __launch_bounds__(1024) void m4rm_persistent(const MulDesc* __restrict__ ds,
                                                         const BatchItem* __restrict__ items, int nitems,
                                                         int* __restrict__ counter) {
@@ -1234,6 +1234,9 @@ __global__ __launch_bounds__(1024) void m4rm_persistent(const MulDesc* __restric
       case 18: run_kappa<V18>(kappa, d, it.tm, it.tn); break;
       case 19: run_kappa<V19>(kappa, d, it.tm, it.tn); break;
       case 20: run_kappa<V20>(kappa, d, it.tm, it.tn); break;
+      case 16: persistent_tile<V16>(d, it.tm, it.tn); break;
+      case 17: persistent_tile<V17>(d, it.tm, it.tn); break;
+      case 11: persistent_tile<V11>(d, it.tm, it.tn); break;
       default: run_kappa<V4>(kappa, d, it.tm, it.tn); break;
     }
   }
@@ -1393,7 +1396,7 @@ gf2_status m4rm_launch_group(const MulDesc* descs, int count, int variant, hipSt
 
 bool m4rm_batchable(int variant) {
   switch (variant) {
-    case 1: case 2: case 3: case 4: case 12: case 13: case 18: case 19: case 20: return true;
+    case 1: case 2: case 3: case 4: case 11: case 12: case 13: case 16: case 17: case 18: case 19: case 20: return true;
     default: return false;
   }
 }

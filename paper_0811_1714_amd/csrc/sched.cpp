@@ -9,11 +9,11 @@ namespace gf2 {
 namespace {
 
 // The candidate list: every tile the persistent batch kernel runs (two-table tiles of 1024 to
-// 128 rows, four-table tiles of 1024 to 256, eight-table tiles of 1024 and 512) with 8-bit
+// 128 rows, four-table tiles of 2048 to 256, eight-table tiles of 2048 to 512) with 8-bit
 // tables, the short ones also with 7- to 5-bit tables (a product of few rows builds its tables
-// for few lookups), k-split and one-level Strassen-Winograd forms, then schedules that only run
-// as grouped launches (the tallest tiles, the int8 matrix core, the popcount kernel).  Index
-// order is part of the ABI (schedule model outputs follow it).
+// for few lookups), k-split and one-level Strassen-Winograd forms, and schedules that only run
+// as grouped launches (the 1536-row two-table tile, the int8 matrix core, the popcount kernel).
+// Index order is part of the ABI (schedule model outputs follow it); later additions are appended.
 const gf2_schedule kCandidates[] = {
     {GF2_KERNEL_M4RM, 1, 0, 1, 0, 8},      //  0: t=2, 1024 rows x 1024 columns
     {GF2_KERNEL_M4RM, 2, 0, 1, 0, 8},      //  1: t=2, 512 rows
@@ -39,9 +39,11 @@ const gf2_schedule kCandidates[] = {
     {GF2_KERNEL_M4RM, 1, 1024, 1, 0, 8},   // 21: Strassen-Winograd above 1024, t=2 1024-row leaves
     {GF2_KERNEL_M4RM, 18, 1024, 1, 0, 8},  // 22: Strassen-Winograd above 1024, t=4 1024-row leaves
     {GF2_KERNEL_M4RM, 0, 0, 1, 0, 8},      // 23: t=2, 1536 rows (grouped launch)
-    {GF2_KERNEL_M4RM, 16, 0, 1, 0, 8},     // 24: t=4, 2048 rows (grouped launch)
+    {GF2_KERNEL_M4RM, 16, 0, 1, 0, 8},     // 24: t=4, 2048 rows
     {GF2_KERNEL_MFMA, 0, 0, 1, 0, 8},      // 25: int8 matrix core
     {GF2_KERNEL_CUBIC, 0, 0, 1, 0, 8},     // 26: popcount
+    {GF2_KERNEL_M4RM, 17, 0, 1, 0, 8},     // 27: t=4, 1536 rows
+    {GF2_KERNEL_M4RM, 11, 0, 1, 0, 8},     // 28: t=8, 2048 rows x 256 columns
 };
 constexpr int kNumCandidates = sizeof(kCandidates) / sizeof(kCandidates[0]);
 
@@ -59,7 +61,7 @@ const gf2_schedule& candidate(int i) { return kCandidates[i]; }
 int fixed_candidate(int64_t m, int64_t k, int64_t n) {
   int best = 0;
   double best_cost = 0;
-  for (int c = 0; c <= 8; ++c) {
+  for (int c : {0, 1, 2, 3, 4, 5, 6, 7, 8, 24, 27, 28}) {
     const gf2_schedule& s = kCandidates[c];
     const int64_t bm = m4rm_tile_rows(s.variant), tw = m4rm_tile_words(s.variant), pr = m4rm_phase_rows(s.variant);
     const double tiles = (double)((m + bm - 1) / bm) * (double)((words(n) + tw - 1) / tw);

@@ -136,6 +136,103 @@ __global__ void xor2_kernel(OView o, QView a, QView b) {
   }
 }
 
+// Two recursion levels of Algorithm 4 in one pass each, for a node whose quadrants and whose
+// children's quadrants all split exactly (m a multiple of 4, k and n of 256): every operand is
+// then a block of 4 x 4 equal sub-quadrants, X[i][j] = rows i*R4.., words j*W4...
+//   pre:  from A's (B's) sixteen sub-quadrants, the node's S0..S3 (T0..T3) and every child's
+//         S'0..S'3 (T'0..T'3), the child operands being {A_NW, A_NE, S3, A_SE, S0, S1, S2}
+//         (B: {B_NW, B_SW, B_SE, T3, T0, T1, T2}) as in the products P0..P6;
+//   post: from the 49 leaf products, each child's U0, U4, U5, U6 (its output's quadrants, i.e.
+//         the node's P_c by sub-quadrant) and from those the node's C quadrants.
+// A pass reads each input word once, so the node's own P0..P6 never go through memory.
+__device__ __forceinline__ void s_of(int kind, const uint64_t (&q)[4], uint64_t (&o)[4]) {
+  // q = NW, NE, SW, SE of one operand at one position; o = S0..S3 (kind 0) or T0..T3 (kind 1).
+  if (kind == 0) {
+    o[0] = q[2] ^ q[3];
+    o[1] = o[0] ^ q[0];
+    o[2] = q[0] ^ q[2];
+    o[3] = q[1] ^ o[1];
+  } else {
+    o[0] = q[1] ^ q[0];
+    o[1] = q[3] ^ o[0];
+    o[2] = q[3] ^ q[1];
+    o[3] = o[1] ^ q[2];
+  }
+}
+
+__global__ void strassen_pre2_kernel(Pre2Args args) {
+  const Pre2Op& a = args.op[blockIdx.y];
+  const int64_t total = a.R4 * a.W4;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / a.W4, w = i - r * a.W4;
+    uint64_t x[4][4];
+#pragma unroll
+    for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 4; ++bj) x[bi][bj] = a.in[(bi * a.R4 + r) * a.ldi + bj * a.W4 + w];
+    // The node's quadrants by sub-position qi, qj, then its S (T), written by sub-position.
+    uint64_t nodeq[4][4], st[4][4];   // [sub-position][NW, NE, SW, SE] and [sub-position][S0..S3]
+#pragma unroll
+    for (int qi = 0; qi < 2; ++qi)
+#pragma unroll
+      for (int qj = 0; qj < 2; ++qj) {
+        const int sp = 2 * qi + qj;
+        nodeq[sp][0] = x[qi][qj];
+        nodeq[sp][1] = x[qi][2 + qj];
+        nodeq[sp][2] = x[2 + qi][qj];
+        nodeq[sp][3] = x[2 + qi][2 + qj];
+        s_of(a.kind, nodeq[sp], st[sp]);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) a.node[t][(qi * a.R4 + r) * a.ldn + qj * a.W4 + w] = st[sp][t];
+      }
+    // Child operand c by sub-position: a node quadrant (index) or one of its S (T) (4 + index).
+    constexpr int A_OPS[7] = {0, 1, 4 + 3, 3, 4 + 0, 4 + 1, 4 + 2};
+    constexpr int B_OPS[7] = {0, 2, 3, 4 + 3, 4 + 0, 4 + 1, 4 + 2};
+#pragma unroll
+    for (int c = 0; c < 7; ++c) {
+      const int src = a.kind == 0 ? A_OPS[c] : B_OPS[c];
+      uint64_t q[4], o[4];
+#pragma unroll
+      for (int sp = 0; sp < 4; ++sp) q[sp] = src < 4 ? nodeq[sp][src] : st[sp][src - 4];
+      s_of(a.kind, q, o);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) a.child[c][t][r * a.ldc + w] = o[t];
+    }
+  }
+}
+
+__global__ void strassen_post2_kernel(Post2Op a) {
+  const int64_t total = a.R4 * a.W4;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / a.W4, w = i - r * a.W4;
+    const int64_t off = r * a.ldp + w;
+    uint64_t v[7][4];   // child c's output by sub-position: U0 (NW), U4 (NE), U5 (SW), U6 (SE)
+#pragma unroll
+    for (int c = 0; c < 7; ++c) {
+      uint64_t p[7];
+#pragma unroll
+      for (int j = 0; j < 7; ++j) p[j] = a.P[c][j][off];
+      const uint64_t u1 = p[0] ^ p[5], u2 = u1 ^ p[6];
+      v[c][0] = p[0] ^ p[1];
+      v[c][1] = u1 ^ p[4] ^ p[2];
+      v[c][2] = u2 ^ p[3];
+      v[c][3] = u2 ^ p[4];
+    }
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp) {
+      const int qi = sp >> 1, qj = sp & 1;
+      const uint64_t u1 = v[0][sp] ^ v[5][sp], u2 = u1 ^ v[6][sp];
+      const uint64_t out[4] = {v[0][sp] ^ v[1][sp], u1 ^ v[4][sp] ^ v[2][sp], u2 ^ v[3][sp], u2 ^ v[4][sp]};
+#pragma unroll
+      for (int Q = 0; Q < 4; ++Q) {
+        const int Qi = Q >> 1, Qj = Q & 1;
+        uint64_t* cp = a.C + ((2 * Qi + qi) * a.R4 + r) * a.ldc + (2 * Qj + qj) * a.W4 + w;
+        *cp = a.mode == OUT_STORE ? out[Q] : (*cp ^ out[Q]);
+      }
+    }
+  }
+}
+
 unsigned grid_for(int64_t total) {
   int64_t b = (total + kThreads - 1) / kThreads;
   const int64_t cap = 256 * 16;
@@ -156,6 +253,26 @@ gf2_status xor2(const OView& o, const QView& a, const QView& b, int trace_kind, 
   TraceScope trace(trace_kind, 1, 24.0 * o.rows * o.wds, s);
   hipLaunchKernelGGL(xor2_kernel, dim3(grid_for(o.rows * o.wds)), dim3(kThreads), 0, s, o, a, b);
   return hip_check(hipGetLastError(), "xor2 launch");
+}
+
+gf2_status strassen_pre2(const Pre2Op& a_side, const Pre2Op& b_side, hipStream_t s) {
+  Pre2Args args;
+  args.op[0] = a_side;
+  args.op[1] = b_side;
+  const int64_t mx = std::max(a_side.R4 * a_side.W4, b_side.R4 * b_side.W4);
+  if (mx <= 0) return GF2_OK;
+  const double bytes = 8.0 * (a_side.R4 * a_side.W4 + b_side.R4 * b_side.W4) * (16 + 16 + 28);
+  TraceScope trace(GF2_TRACE_PRE, 2, bytes, s);
+  hipLaunchKernelGGL(strassen_pre2_kernel, dim3(grid_for(mx), 2), dim3(kThreads), 0, s, args);
+  return hip_check(hipGetLastError(), "strassen_pre2 launch");
+}
+
+gf2_status strassen_post2(const Post2Op& a, hipStream_t s) {
+  const int64_t total = a.R4 * a.W4;
+  if (total <= 0) return GF2_OK;
+  TraceScope trace(GF2_TRACE_POST, 1, 8.0 * total * (49 + 16 * (a.mode == OUT_STORE ? 1 : 2)), s);
+  hipLaunchKernelGGL(strassen_post2_kernel, dim3(grid_for(total)), dim3(kThreads), 0, s, a);
+  return hip_check(hipGetLastError(), "strassen_post2 launch");
 }
 
 // Multi-op launches: blockIdx.y selects the op; x blocks stride over its words.

@@ -91,6 +91,19 @@ def test_two_temporary_schedule_same_bits(g, m, k, n, cutoff, variant):
     assert np.array_equal(low, fast)
 
 
+@pytest.mark.parametrize("m,k,n,cutoff,acc", [(1024, 1024, 1024, 256, False), (2048, 1536, 1280, 384, True),
+                                               (1024, 2048, 512, 200, False)])
+def test_fused_two_level_passes(g, m, k, n, cutoff, acc):
+    """Two recursion levels with exact splits (m a multiple of 4, k and n of 256) run both levels'
+    pre-additions in one pass and both levels' post-additions in another; the bits must equal the
+    oracle's and those of the same product one level deeper and one level shallower."""
+    print(f"fused passes {(m, k, n)} cutoff {cutoff} accumulate {acc}", flush=True)
+    two = run_and_check(g, m, k, n, schedule=M4RM(1, cutoff), accumulate=acc, seed=33, ldc_pad=1, lda_pad=1)
+    one = run_and_check(g, m, k, n, schedule=M4RM(1, 2 * cutoff), accumulate=acc, seed=33, ldc_pad=1, lda_pad=1)
+    three = run_and_check(g, m, k, n, schedule=M4RM(1, cutoff // 2), accumulate=acc, seed=33, ldc_pad=1, lda_pad=1)
+    assert np.array_equal(two, one) and np.array_equal(two, three)
+
+
 def test_two_temporary_schedule_falls_back(g):
     """Where the two-temporary form does not apply (odd rows, columns not a multiple of 128,
     accumulation) the call runs breadth-first, with the same bits."""
