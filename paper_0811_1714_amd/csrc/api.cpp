@@ -444,8 +444,10 @@ bool splittable(int64_t m, int64_t k, int64_t n, int64_t cutoff) {
 // post-additions after, so both lists run in creation order: pre-ops parents first,
 // post-ops children first; the leaves run all at once in between.  ``base`` == nullptr
 // only sizes the workspace.
+// ``no_p``: the node's P0..P6 are not allocated (the fused two-level passes never use them; the
+// plan's post-addition records then hold views of null buffers and must not be launched).
 void plan_node(StrassenPlan& pl, uint64_t* base, const View& A, const View& B, uint64_t* C, int64_t ldc,
-               int out_mode, int64_t cutoff, int odd, int depth = 0) {
+               int out_mode, int64_t cutoff, int odd, int depth = 0, bool no_p = false) {
   const int64_t m = A.rows, k = A.cols, n = B.cols;
   if (!splittable(m, k, n, cutoff)) {
     pl.leaves.push_back(make_desc(A, B, C, ldc, out_mode));
@@ -487,7 +489,7 @@ void plan_node(StrassenPlan& pl, uint64_t* base, const View& A, const View& B, u
   uint64_t* P[7];
   for (int i = 0; i < 4; ++i) S[i] = alloc((size_t)(m0 * k0w));
   for (int i = 0; i < 4; ++i) T[i] = alloc((size_t)(k0 * n0w));
-  for (int i = 0; i < 7; ++i) P[i] = alloc((size_t)(m0 * n0w));
+  for (int i = 0; i < 7; ++i) P[i] = no_p ? nullptr : alloc((size_t)(m0 * n0w));
 
   PreOp ps;
   ps.kind = 0;
@@ -641,15 +643,26 @@ void plan_expansions(ProductPlan& pp, uint64_t* xbase, int kappa, const std::vec
   }
 }
 
+// Two recursion levels with every split exact (padding rule, m a multiple of 4, k and n of 256,
+// the node and its children splittable, the grandchildren not): the single-product executor then
+// runs both levels' passes fused (strassen_pre2 / strassen_post2), and the node's P0..P6 are not
+// needed.  One predicate decides both the plan's workspace and the executor's path.
+bool fused_two_levels(int64_t m, int64_t k, int64_t n, const gf2_schedule& s) {
+  return s.odd == GF2_ODD_PAD && m % 4 == 0 && k % 256 == 0 && n % 256 == 0 && splittable(m, k, n, s.cutoff) &&
+         splittable(m / 2, k / 2, n / 2, s.cutoff) && !splittable(m / 4, k / 4, n / 4, s.cutoff);
+}
+
+// ``fusable``: the plan is for the single-product executor, which fuses the passes where
+// fused_two_levels holds (batch plans launch every level's passes and keep all buffers).
 void plan_product(ProductPlan& pp, uint64_t* base, uint64_t* C, int64_t ldc, const uint64_t* A, int64_t lda,
                   const uint64_t* B, int64_t ldb, int64_t m, int64_t k, int64_t n, bool accumulate,
-                  const gf2_schedule& s) {
+                  const gf2_schedule& s, bool fusable = false) {
   const int out = accumulate ? OUT_XOR : OUT_STORE;
   const View Av{A, lda, m, k}, Bv{B, ldb, k, n};
   const bool narrow = s.kernel == GF2_KERNEL_M4RM && kappa_of(s) < 8;
   std::vector<MulDesc*> base_ds;
   if (splittable(m, k, n, s.cutoff)) {
-    plan_node(pp.st, base, Av, Bv, C, ldc, out, s.cutoff, s.odd);
+    plan_node(pp.st, base, Av, Bv, C, ldc, out, s.cutoff, s.odd, 0, fusable && fused_two_levels(m, k, n, s));
     for (MulDesc& d : pp.st.leaves) base_ds.push_back(&d);
     for (auto& f : pp.st.kfix) base_ds.push_back(&f.second);
     for (MulDesc& d : pp.st.fix) base_ds.push_back(&d);
@@ -666,7 +679,7 @@ void plan_product(ProductPlan& pp, uint64_t* base, uint64_t* C, int64_t ldc, con
 
 size_t fast_workspace_words(int64_t m, int64_t k, int64_t n, const gf2_schedule& s) {
   ProductPlan pp;
-  plan_product(pp, nullptr, nullptr, words(n), nullptr, words(k), nullptr, words(n), m, k, n, false, s);
+  plan_product(pp, nullptr, nullptr, words(n), nullptr, words(k), nullptr, words(n), m, k, n, false, s, true);
   return pp.total_words();
 }
 
@@ -730,9 +743,12 @@ gf2_status execute_in(uint64_t* C, int64_t ldc, const uint64_t* A, int64_t lda, 
                       uint64_t* ws) {
   gf2_status r = GF2_OK;
   ProductPlan pp;
-  plan_product(pp, ws, C, ldc, A, lda, B, ldb, m, k, n, accumulate, s);
+  plan_product(pp, ws, C, ldc, A, lda, B, ldb, m, k, n, accumulate, s, true);
   uint64_t* scratch = ws ? ws + pp.st.ws_words + pp.x_words : nullptr;
-  if (!pp.st.leaves.empty() && two_level_exact(pp.st, m, k, n)) {
+  const bool fused = fused_two_levels(m, k, n, s);
+  if (fused && !two_level_exact(pp.st, m, k, n))
+    return set_error(GF2_ERR_UNSUPPORTED, "internal: a fused two-level plan has an unexpected shape");
+  if (fused) {
     // A node and its seven children with every split exact: both levels' pre-additions in one
     // pass, the leaves, both levels' post-additions in one pass.
     const PreOp& ra = pp.st.pre[0];

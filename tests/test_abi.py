@@ -125,11 +125,15 @@ def test_two_temporary_workspace():
     fast = g.Schedule(g.KERNEL_M4RM, 1, 256, 1, 0, 0, g.MEM_FAST)
     # 1024^3: X, Y 512 x 8 words each; a 512^3 product one level down: 15 quadrants of 256 x 4 words.
     assert g.workspace_bytes(1024, 1024, 1024, low) == (2 * 512 * 8 + 15 * 256 * 4) * 8
-    assert g.workspace_bytes(1024, 1024, 1024, fast) == (15 * 512 * 8 + 7 * 15 * 256 * 4) * 8
-    # 32768^3 over 8192-row leaves: 1320 MiB breadth-first, 184 MiB with two temporaries.
+    # Breadth-first, two exact levels: the passes of both levels are fused, so the top node keeps
+    # only its S and T (8 quadrants of 512 x 8 words); each child its 15 of 256 x 4.
+    assert g.workspace_bytes(1024, 1024, 1024, fast) == (8 * 512 * 8 + 7 * 15 * 256 * 4) * 8
+    # Not exact (1000 columns): the top node's P0..P6 are kept too.
+    assert g.workspace_bytes(1024, 1024, 1000, fast) > g.workspace_bytes(1024, 1024, 1024, fast)
+    # 32768^3 over 8192-row leaves: 1096 MiB breadth-first, 184 MiB with two temporaries.
     big_low = g.Schedule(g.KERNEL_M4RM, 16, 8192, 1, 0, 0, g.MEM_LOW)
     big_fast = g.Schedule(g.KERNEL_M4RM, 16, 8192, 1, 0, 0, g.MEM_FAST)
-    assert g.workspace_bytes(32768, 32768, 32768, big_fast) == 1320 << 20
+    assert g.workspace_bytes(32768, 32768, 32768, big_fast) == 1096 << 20
     assert g.workspace_bytes(32768, 32768, 32768, big_low) == 184 << 20
     # Odd rows: the two-temporary form does not apply, the figure is the breadth-first one.
     assert g.workspace_bytes(1025, 1024, 1024, low) == g.workspace_bytes(1025, 1024, 1024, fast)
