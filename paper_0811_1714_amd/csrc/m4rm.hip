@@ -1050,48 +1050,72 @@ struct PolicyT8 {
 };
 
 // Algorithm 1 as it stands, without the row blocking of Algorithm 2 (the ablation's first arm):
-// for each 8-row stripe of B, ONE table of the 256 combinations of the stripe's rows serves every
-// row of A, and C is read and written in global memory once per stripe.  A workgroup owns one
-// 64-bit column of C over all m rows (so its table entries are single words): it builds the
-// stripe's table -- 32 groups of 8 entries, each group a Gray walk in which every entry after the
-// first costs one row addition -- then adds T[x_j] into C[j] for every row j.
+// for each 8-row stripe of B, one table of the 256 combinations of the stripe's rows serves every
+// row of A, and C is read and written in global memory once per stripe (2mnk/64 bytes in all,
+// which the blocked algorithms avoid).  Parallelised over blocks of C: a workgroup owns a
+// BM-row x TW-word block, builds its own copy of the stripe's table restricted to its TW words
+// (32 groups of 8 entries, each group a Gray walk in which every entry after the first costs one
+// row addition), then adds T[x_j] into C[j] in global memory for every row j of its block.
+// Lane w = tid % TW owns word w of the block, so each row's TW words are one coalesced segment.
 struct PolicyAlg1 {
-  static constexpr int BM = 1 << 30, TW = 1, NT = 256, PR = KB, LDS_BYTES = 256 * 8;
-  __device__ __forceinline__ static void run(const MulDesc& d, int, int tn, char* tabc) {
-    uint64_t* tab = reinterpret_cast<uint64_t*>(tabc);
-    const int tid = threadIdx.x;
-    const int64_t Wn = words(d.n);
-    const uint64_t tail = ((d.n & 63) && tn == Wn - 1) ? ((1ull << (d.n & 63)) - 1) : ~0ull;
-    gword* col = (gword*)(d.C + tn);
-    if (d.out == OUT_STORE)
-      for (int64_t r = tid; r < d.m; r += NT) col[r * d.ldc] = 0;
+  static constexpr int BM = 512, TW = 8, NT = 256, PR = KB, LDS_BYTES = 256 * TW * 8;
+  static constexpr int LANES = NT / TW, UNROLL = 4;
+  __device__ __forceinline__ static void run(const MulDesc& d, int tm, int tn, char* tabc) {
+    uint64_t* tab = reinterpret_cast<uint64_t*>(tabc);  // tab[x * TW + w]
+    const int tid = threadIdx.x, w = tid % TW, lane = tid / TW;
+    const int64_t Wn = words(d.n), col = (int64_t)tn * TW + w;
+    const bool valid = col < Wn;
+    const uint64_t tail = ((d.n & 63) && col == Wn - 1) ? ((1ull << (d.n & 63)) - 1) : ~0ull;
+    const int64_t r0 = (int64_t)tm * BM;
+    const int rows = (int)(d.m - r0 < BM ? d.m - r0 : BM);
+    gword* cb = (gword*)(d.C + r0 * d.ldc + col);
+    const uint8_t* ab = reinterpret_cast<const uint8_t*>(d.A + r0 * d.lda);
+    if (d.out == OUT_STORE && valid)
+      for (int r = lane; r < rows; r += LANES) cb[r * d.ldc] = 0;
     const int nstripes = (d.k + KB - 1) / KB;
-    const int grp = tid >> 3, low = tid & 7;                // entry group (index bits 3..7), lane in it
     for (int p = 0; p < nstripes; ++p) {
       const int64_t kp = (int64_t)p * KB;
-      if (low == 0) {
-        uint64_t rows[KB];
+      {
+        uint64_t brow[KB];
 #pragma unroll
-        for (int b = 0; b < KB; ++b) rows[b] = kp + b < d.k ? d.B[(kp + b) * d.ldb + tn] & tail : 0;
+        for (int b = 0; b < KB; ++b) brow[b] = (valid && kp + b < d.k) ? d.B[(kp + b) * d.ldb + col] & tail : 0;
         uint64_t v = 0;
 #pragma unroll
         for (int b = 3; b < KB; ++b)
-          if ((grp >> (b - 3)) & 1) v ^= rows[b];
-        tab[grp << 3] = v;
+          if ((lane >> (b - 3)) & 1) v ^= brow[b];
+        tab[(lane << 3) * TW + w] = v;
 #pragma unroll
         for (int i = 1; i < 8; ++i) {
-          v ^= rows[__builtin_ctz(i)];
-          tab[(grp << 3) | (i ^ (i >> 1))] = v;
+          v ^= brow[__builtin_ctz(i)];
+          tab[((lane << 3) | (i ^ (i >> 1))) * TW + w] = v;
         }
       }
       __syncthreads();
-      for (int64_t r = tid; r < d.m; r += NT) {
-        const uint32_t x = reinterpret_cast<const uint8_t*>(d.A + r * d.lda)[p];
-        const uint64_t t = tab[x];
-        if (d.out == OUT_ATOMIC) {
-          if (t) atomicXor(reinterpret_cast<unsigned long long*>(d.C + r * d.ldc + tn), (unsigned long long)t);
-        } else {
-          col[r * d.ldc] ^= t;
+      if (valid) {
+        // UNROLL rows per pass, all loads before the stores, so that the rows' loads overlap.
+        for (int r = lane; r < rows; r += UNROLL * LANES) {
+          uint32_t x[UNROLL];
+          uint64_t c[UNROLL];
+#pragma unroll
+          for (int u = 0; u < UNROLL; ++u) {
+            const int rr = r + u * LANES;
+            x[u] = rr < rows ? ab[(int64_t)rr * d.lda * 8 + p] : 0;
+            c[u] = (rr < rows && d.out != OUT_ATOMIC) ? cb[rr * d.ldc] : 0;
+          }
+#pragma unroll
+          for (int u = 0; u < UNROLL; ++u) {
+            const int rr = r + u * LANES;
+            if (rr < rows) {
+              const uint64_t t = tab[x[u] * TW + w];
+              if (d.out == OUT_ATOMIC) {
+                if (t)
+                  atomicXor(reinterpret_cast<unsigned long long*>(d.C + (r0 + rr) * d.ldc + col),
+                            (unsigned long long)t);
+              } else {
+                cb[rr * d.ldc] = c[u] ^ t;
+              }
+            }
+          }
         }
       }
       __syncthreads();

@@ -160,8 +160,11 @@ __device__ __forceinline__ void s_of(int kind, const uint64_t (&q)[4], uint64_t 
   }
 }
 
-__global__ void strassen_pre2_kernel(Pre2Args args) {
-  const Pre2Op& a = args.op[blockIdx.y];
+// KIND (0: the A side, 1: the B side) is a template argument so that the child operands'
+// sources below are compile-time indices: with a run-time kind the private arrays they index
+// would live in scratch memory.
+template <int KIND>
+__device__ __forceinline__ void strassen_pre2_side(const Pre2Op& a) {
   const int64_t total = a.R4 * a.W4;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t r = i / a.W4, w = i - r * a.W4;
@@ -181,7 +184,7 @@ __global__ void strassen_pre2_kernel(Pre2Args args) {
         nodeq[sp][1] = x[qi][2 + qj];
         nodeq[sp][2] = x[2 + qi][qj];
         nodeq[sp][3] = x[2 + qi][2 + qj];
-        s_of(a.kind, nodeq[sp], st[sp]);
+        s_of(KIND, nodeq[sp], st[sp]);
 #pragma unroll
         for (int t = 0; t < 4; ++t) a.node[t][(qi * a.R4 + r) * a.ldn + qj * a.W4 + w] = st[sp][t];
       }
@@ -190,15 +193,23 @@ __global__ void strassen_pre2_kernel(Pre2Args args) {
     constexpr int B_OPS[7] = {0, 2, 3, 4 + 3, 4 + 0, 4 + 1, 4 + 2};
 #pragma unroll
     for (int c = 0; c < 7; ++c) {
-      const int src = a.kind == 0 ? A_OPS[c] : B_OPS[c];
+      const int src = KIND == 0 ? A_OPS[c] : B_OPS[c];
       uint64_t q[4], o[4];
 #pragma unroll
       for (int sp = 0; sp < 4; ++sp) q[sp] = src < 4 ? nodeq[sp][src] : st[sp][src - 4];
-      s_of(a.kind, q, o);
+      s_of(KIND, q, o);
 #pragma unroll
       for (int t = 0; t < 4; ++t) a.child[c][t][r * a.ldc + w] = o[t];
     }
   }
+}
+
+__global__ void strassen_pre2_kernel(Pre2Args args) {
+  const Pre2Op& a = args.op[blockIdx.y];
+  if (a.kind == 0)
+    strassen_pre2_side<0>(a);
+  else
+    strassen_pre2_side<1>(a);
 }
 
 __global__ void strassen_post2_kernel(Post2Op a) {

@@ -126,6 +126,16 @@ def test_split_k(g, m, k, n, sk):
     run_and_check(g, m, k, n, schedule=M4RM(2, 0, sk), accumulate=True, seed=6)
 
 
+@pytest.mark.parametrize("m,k,n", [(1000, 777, 1300), (2049, 100, 70), (513, 4100, 520)])
+def test_algorithm1_tile_accumulate_and_split_k(g, m, k, n):
+    # Algorithm 1's tile (C updated in global memory once per stripe) in every output mode:
+    # store, accumulate, and the atomic XOR of a k split.
+    print(f"Algorithm 1 {(m, k, n)}", flush=True)
+    run_and_check(g, m, k, n, schedule=M4RM(21), accumulate=True, seed=16, ldc_pad=1)
+    run_and_check(g, m, k, n, schedule=M4RM(21, 0, 3), seed=17, lda_pad=1)
+    run_and_check(g, m, k, n, schedule=M4RM(21, 0, 5), accumulate=True, seed=18)
+
+
 @pytest.mark.parametrize("m,k,n,cutoff", [(256, 256, 256, 64), (300, 200, 500, 64), (1000, 1000, 1000, 100),
                                           (777, 1500, 1300, 300), (2049, 2049, 2049, 512), (1025, 130, 1025, 64)])
 def test_strassen_winograd_any_cutoff_same_bits(g, m, k, n, cutoff):
