@@ -243,11 +243,11 @@ def configs_bench(g):
         torch.cuda.empty_cache()
 
 
-ABLATION = ((21, "one table per 8-row stripe for all m rows, C in global memory (Alg. 1), n/64 workgroups"),
+ABLATION = ((21, "one table per 8-row stripe for all m rows, C in global memory (Alg. 1), 512 x 512 blocks"),
             (5, "one table per 8-row stripe (Alg. 2), 768 x 2048"), (6, "one table, 512 x 2048"),
             (0, "t = 2 (Alg. 3), 1536 x 1024"), (10, "t = 2, 1408 x 1024"), (1, "t = 2, 1024 x 1024"),
             (2, "t = 2, 512 x 1024"), (11, "t = 8 (Alg. 3), 2048 x 256"), (12, "t = 8, 1024 x 256"),
-            (13, "t = 8, 512 x 256"), (16, "t = 4 (Alg. 3), 2048 x 512"), (17, "t = 4, 1536 x 512"),
+            (13, "t = 8, 512 x 256"), (22, "t = 8, 4096 x 256"), (16, "t = 4 (Alg. 3), 2048 x 512"), (17, "t = 4, 1536 x 512"),
             (18, "t = 4, 1024 x 512"))
 
 

@@ -194,12 +194,22 @@ int32_t gf2_get_policy(void);
  * index.  Synchronises the device.  The result also enters the autotune cache. */
 gf2_status gf2_autotune(int64_t m, int64_t k, int64_t n, double density, int32_t reps, float* ms, int32_t* best);
 /* Throughput timing: the per-product time of each candidate when R copies of the product
- * (shared A and B, separate C; R chosen so one batch holds enough work to fill the GPU,
- * returned in *copies) run as one batch plan.  This is the cost that matters inside
+ * (each with its own A, B and C, as in a real batch; R chosen so one batch holds enough work
+ * to fill the GPU, with at most 512 MiB of operands, returned in *copies) run as one batch plan.  This is the cost that matters inside
  * gf2_mul_batched.  ms as in gf2_autotune; candidates are timed in batch form even when
  * they are not persistent-kernel schedules (they then run as grouped launches). */
 gf2_status gf2_autotune_batch(int64_t m, int64_t k, int64_t n, double density, int32_t reps, float* ms,
                               int32_t* best, int32_t* copies);
+/* Partial re-timing, for refreshing a timing set after a kernel change: as gf2_autotune
+ * (batch == 0) or gf2_autotune_batch (batch != 0), but only the `count` candidates listed in
+ * `candidates` (indices into the candidate list, in any order) are timed; ms[c] of every other
+ * candidate is set to -1 (ms holds gf2_num_candidates() floats).  *copies (may be NULL)
+ * receives the batch's copy count (1 for batch == 0).  The result does not enter the
+ * autotune cache.  GF2_ERR_INVALID_ARG for an index outside [0, gf2_num_candidates()),
+ * count < 0, candidates NULL with count > 0, or a density outside [0, 1], checked before
+ * any device work. */
+gf2_status gf2_autotune_candidates(int64_t m, int64_t k, int64_t n, double density, int32_t reps, int32_t batch,
+                                   const int32_t* candidates, int32_t count, float* ms, int32_t* copies);
 /* Autotune cache persistence (text file: one "m_bucket k_bucket n_bucket index" line per entry). */
 gf2_status gf2_autotune_save(const char* path);
 gf2_status gf2_autotune_load(const char* path);

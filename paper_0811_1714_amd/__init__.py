@@ -98,6 +98,8 @@ def lib():
     L.gf2_autotune.restype = ctypes.c_int
     L.gf2_autotune_batch.argtypes = [I64, I64, I64, ctypes.c_double, I32, P, ctypes.POINTER(I32), ctypes.POINTER(I32)]
     L.gf2_autotune_batch.restype = ctypes.c_int
+    L.gf2_autotune_candidates.argtypes = [I64, I64, I64, ctypes.c_double, I32, I32, P, I32, P, ctypes.POINTER(I32)]
+    L.gf2_autotune_candidates.restype = ctypes.c_int
     L.gf2_autotune_save.argtypes = [ctypes.c_char_p]
     L.gf2_autotune_save.restype = ctypes.c_int
     L.gf2_autotune_load.argtypes = [ctypes.c_char_p]
@@ -326,6 +328,19 @@ def autotune_batch(m, k, n, density=0.5, reps=3):
     _check(lib().gf2_autotune_batch(m, k, n, float(density), int(reps), ms.ctypes.data_as(ctypes.c_void_p),
                                     ctypes.byref(best), ctypes.byref(copies)))
     return ms, best.value, copies.value
+
+
+def autotune_candidates(m, k, n, candidates, density=0.5, reps=3, batch=True):
+    """Time only the listed candidates (alone, or per product inside a batch of copies);
+    returns (ms with -1 for every other candidate, copies).  Does not touch the autotune cache."""
+    import numpy as np
+    ms = np.zeros(num_candidates(), dtype=np.float32)
+    idx = np.ascontiguousarray(np.asarray(candidates, dtype=np.int32))
+    copies = ctypes.c_int32(0)
+    _check(lib().gf2_autotune_candidates(m, k, n, float(density), int(reps), int(bool(batch)),
+                                         idx.ctypes.data_as(ctypes.c_void_p), int(idx.size),
+                                         ms.ctypes.data_as(ctypes.c_void_p), ctypes.byref(copies)))
+    return ms, copies.value
 
 
 def autotune_save(path):

@@ -958,7 +958,10 @@ struct TuneScratch {
   int dev = -1;
 } g_tscr;
 
-gf2_status autotune_shape(int64_t m, int64_t k, int64_t n, double density, int reps, std::vector<float>& ms) {
+// ``only`` (optional): time only the candidates whose entry is nonzero (the others stay at -1);
+// such a partial result does not enter the autotune cache.
+gf2_status autotune_shape(int64_t m, int64_t k, int64_t n, double density, int reps, std::vector<float>& ms,
+                          const std::vector<char>* only = nullptr) {
   std::lock_guard<std::recursive_mutex> tlk(g_tscr_mu);
   const int S = num_candidates();
   ms.assign(S, -1.f);
@@ -997,6 +1000,7 @@ gf2_status autotune_shape(int64_t m, int64_t k, int64_t n, double density, int r
   if ((r = hip_check(hipEventCreate(&e1), "hipEventCreate")) != GF2_OK) { (void)hipEventDestroy(e0); return r; }
   std::vector<float> t(reps);
   for (int c = 0; c < S; ++c) {
+    if (only && !(*only)[c]) continue;
     const gf2_schedule& s = candidate(c);
     if (execute(C, Wn, A, Wk, B, Wn, m, k, n, false, s, st) != GF2_OK) continue;   // warm-up
     bool ok = true;
@@ -1012,18 +1016,18 @@ gf2_status autotune_shape(int64_t m, int64_t k, int64_t n, double density, int r
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   g_err[0] = 0;
-  {
+  if (!only) {
     std::lock_guard<std::mutex> g(g_tune_mu);
     g_tune[TuneKey{tune_bucket(m), tune_bucket(k), tune_bucket(n)}] = ms;
+    ++g_policy_epoch;
   }
-  ++g_policy_epoch;
   return hip_check(hipStreamSynchronize(st), "hipStreamSynchronize");
 }
 
 struct BatchPlanImpl;
 gf2_status build_batch_plan(const gf2_problem* probs, int64_t count, BatchPlanImpl& P);
 gf2_status autotune_batch_shape(int64_t m, int64_t k, int64_t n, double density, int reps, std::vector<float>& ms,
-                                int& copies);
+                                int& copies, const std::vector<char>* only = nullptr);
 
 int argmin_allowed(const std::vector<float>& v, bool batch) {
   int best = -1;
@@ -1048,6 +1052,10 @@ int choose_candidate(int64_t m, int64_t k, int64_t n, bool batch, hipStream_t s,
       int best = -1;
       for (int c = 0; c < S; ++c)
         if ((!batch || batch_allowed(c)) && (best < 0 || yy[c] < yy[best])) best = c;
+      if (best >= 0 && batch) {
+        const int f = fixed_candidate(m, k, n);
+        return model_or_fixed(best, yy[best], f, yy[f]);
+      }
       if (best >= 0) return best;
     }
   } else if (policy == GF2_POLICY_AUTOTUNE && m > 0 && k > 0 && n > 0) {
@@ -1226,14 +1234,17 @@ gf2_status build_batch_plan(const gf2_problem* probs, int64_t count, BatchPlanIm
   std::vector<int> model_pick;
   if (g_policy.load() == GF2_POLICY_MODEL && model_available()) {
     std::vector<float> feats;
+    std::vector<int> fixed;
     for (int64_t i = 0; i < count; ++i)
-      if (probs[i].schedule < 0)
+      if (probs[i].schedule < 0) {
         feats.insert(feats.end(), {(float)std::log2((double)std::max<int64_t>(probs[i].m, 1)),
                                    (float)std::log2((double)std::max<int64_t>(probs[i].k, 1)),
                                    (float)std::log2((double)std::max<int64_t>(probs[i].n, 1)), 0.5f});
+        fixed.push_back(fixed_candidate(probs[i].m, probs[i].k, probs[i].n));
+      }
     std::vector<uint8_t> allowed(num_candidates());
     for (int c = 0; c < num_candidates(); ++c) allowed[c] = batch_allowed(c) ? 1 : 0;
-    if ((r = model_choose_batch(feats, allowed.data(), model_pick)) != GF2_OK) return r;
+    if ((r = model_choose_batch(feats, allowed.data(), fixed, model_pick)) != GF2_OK) return r;
   }
   size_t pick = 0, mfma_scratch = 0;
   for (int64_t i = 0; i < count; ++i) {
@@ -1389,7 +1400,7 @@ constexpr size_t kBatchCacheMax = 8;
 
 // Per-product time of every candidate inside a batch of R copies of the product.
 gf2_status autotune_batch_shape(int64_t m, int64_t k, int64_t n, double density, int reps, std::vector<float>& ms,
-                                int& copies) {
+                                int& copies, const std::vector<char>* only) {
   std::lock_guard<std::recursive_mutex> tlk(g_tscr_mu);
   const int S = num_candidates();
   ms.assign(S, -1.f);
@@ -1398,17 +1409,21 @@ gf2_status autotune_batch_shape(int64_t m, int64_t k, int64_t n, double density,
   if (reps < 1) reps = 1;
   // Enough copies that even the tallest persistent tile (1024 rows x 16 words) gives ~2048
   // tiles, i.e. the batch fills every compute unit several times over, as in a real batch.
+  // Every copy has its own A, B and C (at most 512 MiB in all): with shared operands the
+  // re-reads of A and B by a product's tiles would hit in cache across copies, which favours
+  // the tiles that re-read operands most (the narrow ones) over what a real batch sees.
   const int64_t Wk = words(k), Wn = words(n);
   const double vol = (double)m * (double)k * (double)n;
   const int64_t tiles1024 = ((m + 1023) / 1024) * ((Wn + 15) / 16);
+  const int64_t per_copy = m * Wk + k * Wn + m * Wn;   // words
   int64_t R = std::max<int64_t>((2048 + tiles1024 - 1) / tiles1024, (int64_t)std::llround(8e8 / vol));
   R = std::max<int64_t>(2, std::min<int64_t>(R, 512));
-  R = std::max<int64_t>(1, std::min<int64_t>(R, (int64_t)((512ll << 20) / (8 * m * Wn))));
+  R = std::max<int64_t>(1, std::min<int64_t>(R, (int64_t)((512ll << 20) / (8 * per_copy))));
   copies = (int)R;
   int dev = 0;
   gf2_status r = hip_check(hipGetDevice(&dev), "hipGetDevice");
   if (r != GF2_OK) return r;
-  const size_t need = (size_t)(m * Wk + k * Wn + R * m * Wn);
+  const size_t need = (size_t)(R * per_copy);
   if (g_tscr.dev != dev) {
     g_tscr = TuneScratch{};
     g_tscr.dev = dev;
@@ -1425,19 +1440,21 @@ gf2_status autotune_batch_shape(int64_t m, int64_t k, int64_t n, double density,
       return set_error(GF2_ERR_ALLOC, "autotune: hipMalloc of %zu bytes failed", need * 8);
     g_tscr.words = need;
   }
-  uint64_t* A = g_tscr.buf;
-  uint64_t* B = A + m * Wk;
-  uint64_t* C = B + k * Wn;
+  uint64_t* A = g_tscr.buf;                 // R copies of A, then of B, then of C
+  uint64_t* B = A + R * m * Wk;
+  uint64_t* C = B + R * k * Wn;
   hipStream_t st = g_tscr.stream;
-  if ((r = fill_random(A, m * Wk, 0x1234567ull, density, st)) != GF2_OK) return r;
-  if ((r = fill_random(B, k * Wn, 0x7654321ull, density, st)) != GF2_OK) return r;
+  if ((r = fill_random(A, R * m * Wk, 0x1234567ull, density, st)) != GF2_OK) return r;
+  if ((r = fill_random(B, R * k * Wn, 0x7654321ull, density, st)) != GF2_OK) return r;
   std::vector<gf2_problem> probs(R);
   hipEvent_t e0, e1;
   if ((r = hip_check(hipEventCreate(&e0), "hipEventCreate")) != GF2_OK) return r;
   if ((r = hip_check(hipEventCreate(&e1), "hipEventCreate")) != GF2_OK) { (void)hipEventDestroy(e0); return r; }
   std::vector<float> t(reps);
   for (int c = 0; c < S; ++c) {
-    for (int64_t i = 0; i < R; ++i) probs[i] = gf2_problem{A, B, C + i * m * Wn, m, k, n, Wk, Wn, Wn, 0, c};
+    if (only && !(*only)[c]) continue;
+    for (int64_t i = 0; i < R; ++i)
+      probs[i] = gf2_problem{A + i * m * Wk, B + i * k * Wn, C + i * m * Wn, m, k, n, Wk, Wn, Wn, 0, c};
     BatchPlanImpl P;
     if (build_batch_plan(probs.data(), R, P) != GF2_OK || P.enqueue(st) != GF2_OK) continue;
     bool ok = true;
@@ -1596,6 +1613,28 @@ gf2_status gf2_autotune_batch(int64_t m, int64_t k, int64_t n, double density, i
   if (r != GF2_OK) return r;
   if (ms) std::copy(v.begin(), v.end(), ms);
   if (best) *best = argmin_allowed(v, true);
+  if (copies) *copies = R;
+  return GF2_OK;
+}
+
+gf2_status gf2_autotune_candidates(int64_t m, int64_t k, int64_t n, double density, int32_t reps, int32_t batch,
+                                   const int32_t* candidates, int32_t count, float* ms, int32_t* copies) {
+  g_err[0] = 0;
+  if (density < 0 || density > 1) return set_error(GF2_ERR_INVALID_ARG, "density must be in [0, 1]");
+  const int S = num_candidates();
+  if (count < 0 || (count > 0 && !candidates)) return set_error(GF2_ERR_INVALID_ARG, "candidate list is invalid");
+  std::vector<char> only(S, 0);
+  for (int32_t i = 0; i < count; ++i) {
+    if (candidates[i] < 0 || candidates[i] >= S)
+      return set_error(GF2_ERR_INVALID_ARG, "candidate index %d out of range [0, %d)", candidates[i], S);
+    only[candidates[i]] = 1;
+  }
+  std::vector<float> v;
+  int R = 1;
+  const gf2_status r = batch ? autotune_batch_shape(m, k, n, density, reps, v, R, &only)
+                             : autotune_shape(m, k, n, density, reps, v, &only);
+  if (r != GF2_OK) return r;
+  if (ms) std::copy(v.begin(), v.end(), ms);
   if (copies) *copies = R;
   return GF2_OK;
 }

@@ -59,7 +59,13 @@ int fixed_candidate(int64_t m, int64_t k, int64_t n);
 // Schedule model inference on the host copy of the weights: predicted log runtimes.
 bool model_predict(int64_t m, int64_t k, int64_t n, double density, float* out);
 bool model_available();
-gf2_status model_choose_batch(const std::vector<float>& feats_raw, const uint8_t* allowed_host, std::vector<int>& out);
+// Batch schedules under the model policy: the model's candidate replaces the fixed rule's
+// only where it is predicted at least this fraction faster (smaller predicted gains are within
+// the model's error, and end to end they cost more than they save).
+constexpr double kModelBatchMargin = 0.10;
+int model_or_fixed(int pick, float y_pick, int fixed, float y_fixed);
+gf2_status model_choose_batch(const std::vector<float>& feats_raw, const uint8_t* allowed_host,
+                              const std::vector<int>& fixed, std::vector<int>& out);
 bool batch_allowed(int candidate);
 void bump_policy_epoch();   // invalidates cached batch plans after a policy or model change
 

@@ -528,7 +528,12 @@ __device__ __forceinline__ void m4rm2_tile_any(const MulDesc& d, int tm, int tn,
 // ds_read_b128 serves 32 rows.  In lookup instruction h, row r reads table h ^ (r & 7):
 // every 16 lanes then touch eight different tables, i.e. all 64 LDS banks.  Each row's A
 // qword (its eight indices for the phase) is byte-permuted once so that instruction h
-// finds row r's index for table h ^ (r & 7) in byte h.
+// finds row r's index for table h ^ (r & 7) in byte h.  A is loaded in chunks of two
+// phases: lane (row, half j) loads the row's qword of phase 2c + j, so one load instruction
+// covers 32 rows x 16 contiguous bytes, and phase 2c + j takes its qword from the row's
+// half-j lane with a quad broadcast (DPP).  Loading 8 bytes per row per phase instead, one
+// instruction touched 32 cache lines for 256 bytes of indices, four times the lines per
+// index byte of the four-table tile.
 constexpr int T8_WORDS = 4;                 // 256 columns per tile
 
 template <int WAVES, int S, int KAPPA = KB>
@@ -537,15 +542,15 @@ struct Tile8 {
   static constexpr int BM = WAVES * RW;
   static constexpr int HIB = KAPPA - wave_bits<WAVES>();
   static constexpr int PR = 8 * KAPPA;      // rows of B per phase
-  // Loads run DA phases ahead (A indices and B rows), DA = 2 on the short tiles: a ring of NA
-  // sets of A registers and DA sets of B rows, both indexed by the phase modulo 4.
-  static constexpr int DA = S <= 2 ? 2 : 1, NA = 2 * DA;
+  // B rows are loaded DA phases ahead, DA = 2 on the short tiles: a ring of DA sets of B rows
+  // indexed by the phase modulo 4.  A chunks (two phases each) are loaded one chunk ahead.
+  static constexpr int DA = S <= 2 ? 2 : 1;
 };
 
 template <int WAVES, int S, int KAPPA, bool EDGE>
 __device__ __forceinline__ void m4rm8_tile(const MulDesc& d, int tm, int tn, char* tab) {
   using T = Tile8<WAVES, S, KAPPA>;
-  constexpr int DA = T::DA, NA = T::NA;
+  constexpr int DA = T::DA;
   const int tid = threadIdx.x;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int L = tid & 63, r32 = L >> 1, half = L & 1;
@@ -578,10 +583,10 @@ __device__ __forceinline__ void m4rm8_tile(const MulDesc& d, int tm, int tn, cha
   uint4 acc[S];
 #pragma unroll
   for (int s = 0; s < S; ++s) acc[s] = make_uint4(0, 0, 0, 0);
-  uint2 areg[NA][S];
-  auto load_a = [&](int p, uint2 (&dst)[S]) {
+  uint2 ach[2][S];                                      // A chunk c in set c & 1
+  auto load_chunk = [&](int c, uint2 (&dst)[S]) {
 #pragma unroll
-    for (int s = 0; s < S; ++s) dst[s] = bload2(ra, (32 * s + r32) * lda_b + 8 * p);
+    for (int s = 0; s < S; ++s) dst[s] = bload2(ra, (32 * s + r32) * lda_b + 16 * c + 8 * half);
   };
   StripeRows<KAPPA> ring[DA];
   auto fetch = [&](int p, StripeRows<KAPPA>& sr) {
@@ -592,47 +597,52 @@ __device__ __forceinline__ void m4rm8_tile(const MulDesc& d, int tm, int tn, cha
     for (int b = 0; b < KAPPA; ++b) sr.r[b] = bload1(rb, bo[b]);
   };
   if (nphases > 0) {
+    load_chunk(0, ach[0]);
 #pragma unroll
-    for (int i = 0; i < DA; ++i) {                        // phases 0 .. DA-1
-      load_a(i, areg[i]);
-      fetch(i, ring[i]);
-    }
+    for (int i = 0; i < DA; ++i) fetch(i, ring[i]);       // phases 0 .. DA-1
     build_table<WAVES, KAPPA>(tab, 0, w, L, ring[0]);
   }
   __syncthreads();
 
-  // The next phase's loads are issued unconditionally (past the end they load zeros or
-  // unused stride-gap words, with no branch), and the byte permutation is pinned after the
+  // The next loads are issued unconditionally (past the end they load zeros or unused
+  // stride-gap words, with no branch), and a chunk's byte permutation is pinned after the
   // barrier that ends the previous phase (an empty asm on each qword): hoisted above it, it
   // would wait there for loads that have only just been issued.
   auto phase = [&](int p, auto I) {
     constexpr int i = decltype(I)::value;                 // p mod 4
-    uint2 (&cur)[S] = areg[i % NA];
+    constexpr int j = i & 1, cs = i >> 1;                 // phase 2c + j of chunk c, in set cs
+    constexpr int dpp = j ? 0xf5 : 0xa0;                  // quad lanes {1,1,3,3} or {0,0,2,2}
+    uint2 (&cur)[S] = ach[cs];
     fetch(p + DA, ring[i % DA]);
-    load_a(p + DA, areg[(i + DA) % NA]);
-    const uint32_t lb = cb | ((uint32_t)(p & 1) << 16);
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-      asm volatile("" : "+v"(cur[s].x), "+v"(cur[s].y));
-      const uint32_t lo = __builtin_amdgcn_perm(cur[s].y, cur[s].x, sel_lo);
-      const uint32_t hi = __builtin_amdgcn_perm(cur[s].y, cur[s].x, sel_hi);
-      cur[s] = make_uint2(lo, hi);
-    }
-#pragma unroll
-    for (int h = 0; h < 8; h += 2) {
-      // byte0 <- lb ^ table offset, byte1 <- index byte h (of lo or hi), byte2 <- buffer bit
-      constexpr uint32_t base_sel = 0x0c020400u;
-      const uint32_t l0 = lb ^ ((uint32_t)h << 5), l1 = lb ^ ((uint32_t)(h + 1) << 5);
+    if constexpr (j == 0) {
+      load_chunk((p >> 1) + 1, ach[cs ^ 1]);
 #pragma unroll
       for (int s = 0; s < S; ++s) {
-        const uint32_t q = h < 4 ? cur[s].x : cur[s].y;
+        asm volatile("" : "+v"(cur[s].x), "+v"(cur[s].y));
+        const uint32_t lo = __builtin_amdgcn_perm(cur[s].y, cur[s].x, sel_lo);
+        const uint32_t hi = __builtin_amdgcn_perm(cur[s].y, cur[s].x, sel_hi);
+        cur[s] = make_uint2(lo, hi);
+      }
+    }
+    const uint32_t lb = cb | ((uint32_t)(p & 1) << 16);
+    // byte0 <- lb ^ table offset, byte1 <- index byte h (of lo or hi), byte2 <- buffer bit
+    constexpr uint32_t base_sel = 0x0c020400u;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      // The row's permuted qword for this phase, from its half-j lane.
+      const uint32_t qlo = (uint32_t)__builtin_amdgcn_mov_dpp((int)cur[s].x, dpp, 0xf, 0xf, true);
+      const uint32_t qhi = (uint32_t)__builtin_amdgcn_mov_dpp((int)cur[s].y, dpp, 0xf, 0xf, true);
+#pragma unroll
+      for (int h = 0; h < 8; h += 2) {
+        const uint32_t l0 = lb ^ ((uint32_t)h << 5), l1 = lb ^ ((uint32_t)(h + 1) << 5);
+        const uint32_t q = h < 4 ? qlo : qhi;
         const uint32_t a0 = __builtin_amdgcn_perm(q, l0, base_sel + ((uint32_t)(h & 3) << 8));
         const uint32_t a1 = __builtin_amdgcn_perm(q, l1, base_sel + ((uint32_t)((h + 1) & 3) << 8));
         const uint4 t0 = *reinterpret_cast<const uint4*>(tab + a0);
         const uint4 t1 = *reinterpret_cast<const uint4*>(tab + a1);
         acc[s] = xor3v(acc[s], t0, t1);
-        asm volatile("" : "+v"(acc[s].x), "+v"(acc[s].y), "+v"(acc[s].z), "+v"(acc[s].w));
       }
+      asm volatile("" : "+v"(acc[s].x), "+v"(acc[s].y), "+v"(acc[s].z), "+v"(acc[s].w));
     }
     if (p + 1 < nphases) build_table<WAVES, KAPPA>(tab, (p & 1) ^ 1, w, L, ring[(i + 1) % DA]);
     __syncthreads();
@@ -1181,11 +1191,12 @@ template <int K> using V18 = PolicyT4<16, 4, K>;     // t=4, BM 1024
 template <int K> using V19 = PolicyT4<16, 2, K>;     // t=4, BM 512
 template <int K> using V20 = PolicyT4<16, 1, K>;     // t=4, BM 256
 using V21 = PolicyAlg1;           // Algorithm 1: one table per stripe for all m rows, C in global memory
+using V22 = PolicyT8<16, 8>;      // t=8, BM 4096 x 256 columns: two tiles cover 8192 rows
 const Variant kVariants[] = {variant8<V0>(), variantk<V1>(), variantk<V2>(), variantk<V3>(), variantk<V4>(),
                              variant8<V5>(), variant8<V6>(), variant8<V7>(), variant8<V8>(), variant8<V9>(),
                              variant8<V10>(), variant8<V11>(), variantk<V12>(), variantk<V13>(), variant8<V14>(),
                              variant8<V15>(), variant8<V16>(), variant8<V17>(), variantk<V18>(), variantk<V19>(),
-                             variantk<V20>(), variant8<V21>()};
+                             variantk<V20>(), variant8<V21>(), variant8<V22>()};
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
 // The persistent kernel's tables, at file scope so that the tile functions below address
@@ -1379,11 +1390,18 @@ gf2_status m4rm_launch_group(const MulDesc* descs, int count, int variant, hipSt
         break;
       }
   // The four-table tiles address up to 128 rows of A per wave the same way: for A rows of
-  // 2^20 words or more the 1408-row two-table tile runs instead.
+  // 2^20 words or more the 1408-row two-table tile runs instead; the 4096-row eight-table
+  // tile (256 rows per wave) hands such an A to the 2048-row one.
   if (variant_of(variant).tw == T4_WORDS)
     for (int i = 0; i < count; ++i)
       if (descs[i].lda >= (int64_t(1) << 20)) {
         variant = 10;
+        break;
+      }
+  if (variant == 22)
+    for (int i = 0; i < count; ++i)
+      if (descs[i].lda >= (int64_t(1) << 20)) {
+        variant = 11;
         break;
       }
   const Variant& v = variant_of(variant);

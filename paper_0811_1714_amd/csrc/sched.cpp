@@ -100,8 +100,18 @@ bool model_predict(int64_t m, int64_t k, int64_t n, double density, float* out) 
   return true;
 }
 
-// Device inference for many products: returns the argmin candidates (allowed mask on host).
-gf2_status model_choose_batch(const std::vector<float>& feats_raw, const uint8_t* allowed_host, std::vector<int>& out) {
+int model_or_fixed(int pick, float y_pick, int fixed, float y_fixed) {
+  // The model's outputs are predicted natural-log times: its pick must be predicted at least
+  // kModelBatchMargin faster than the fixed rule's candidate to replace it.
+  static const float kLogKeep = (float)std::log(1.0 - kModelBatchMargin);
+  if (pick < 0 || pick == fixed) return fixed;
+  return y_pick - y_fixed < kLogKeep ? pick : fixed;
+}
+
+// Device inference for many products: the batch head's argmin over the allowed candidates,
+// kept only where it beats the fixed rule's candidate (fixed[b]) by the margin above.
+gf2_status model_choose_batch(const std::vector<float>& feats_raw, const uint8_t* allowed_host,
+                              const std::vector<int>& fixed, std::vector<int>& out) {
   const int64_t nb = (int64_t)feats_raw.size() / 4;
   out.assign(nb, -1);
   std::lock_guard<std::mutex> g(g_model_mu);
@@ -148,8 +158,15 @@ gf2_status model_choose_batch(const std::vector<float>& feats_raw, const uint8_t
   if (r == GF2_OK) r = mlp_forward(g_model_dev, dX, nb, NO, dY, dA, nullptr);
   if (r == GF2_OK) r = mlp_argmin(dY, nb, NO, dAllowed, dOut, nullptr);
   if (r == GF2_OK) r = hip_check(hipMemcpy(host_out.data(), dOut, nb * sizeof(int32_t), hipMemcpyDeviceToHost), "hipMemcpy");
+  std::vector<float> y(r == GF2_OK ? fY : 0);
+  if (r == GF2_OK) r = hip_check(hipMemcpy(y.data(), dY, fY * sizeof(float), hipMemcpyDeviceToHost), "hipMemcpy");
   (void)hipFree(buf);
-  for (int64_t b = 0; b < nb; ++b) out[b] = host_out[b] >= kNumCandidates ? host_out[b] - kNumCandidates : -1;
+  if (r != GF2_OK) return r;
+  for (int64_t b = 0; b < nb; ++b) {
+    const int p = host_out[b] >= kNumCandidates ? host_out[b] - kNumCandidates : -1;
+    const float* yb = y.data() + b * NO + kNumCandidates;
+    out[b] = p < 0 ? -1 : model_or_fixed(p, yb[p], fixed[b], yb[fixed[b]]);
+  }
   return r;
 }
 

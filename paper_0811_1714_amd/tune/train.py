@@ -42,6 +42,29 @@ def init_params(S, seed):
     return np.concatenate(parts).astype(np.float32)
 
 
+MARGIN = 0.10   # the library's batch rule (kModelBatchMargin)
+
+
+def unstandardise(params, n_out, tmean, tstd):
+    """Fold per-output target standardisation into the last layer: y = (x W + b) * std + mean."""
+    p = params.copy()
+    fan_in = 64
+    b0 = p.size - n_out
+    w0 = b0 - fan_in * n_out
+    W = p[w0:b0].reshape(fan_in, n_out) * tstd[None, :]
+    p[w0:b0] = W.reshape(-1)
+    p[b0:] = p[b0:] * tstd + tmean
+    return p
+
+
+def margin_rule(pred_log_ms, pick, fixed):
+    """The library's batch rule: the model's pick where its predicted time is at least MARGIN
+    below that of the fixed rule's candidate, else the fixed rule's candidate."""
+    rows = np.arange(len(pick))
+    keep = pred_log_ms[rows, pick] - pred_log_ms[rows, fixed] < np.log(1 - MARGIN)
+    return np.where(keep, pick, fixed)
+
+
 def regret(ms, choice):
     """t(choice)/t(best) - 1 per row (rows whose chosen candidate did not run count as inf)."""
     valid = np.where(ms > 0, ms, np.inf)
@@ -179,14 +202,19 @@ def main():
     history = best[3]
     n = len(fit_idx)
 
-    params = tr.params.cpu().numpy()
+    # The stored model predicts natural-log milliseconds: each head's standardisation is folded
+    # into the output layer (argmin unchanged), so that the library can compare two predicted
+    # times, as its batch rule does (a model pick replaces the fixed rule's only when predicted
+    # at least MARGIN faster).
+    params = unstandardise(tr.params.cpu().numpy().astype(np.float64), NO, tmean, tstd).astype(np.float32)
     norm = np.concatenate([mean, std]).astype(np.float32)
-    pred_ho = tr.predict(Xho)
+    pred_ho = tr.predict(Xho) * tstd + tmean
     lat_ho, thr_ho = ms_ho[:, :S], ms_ho[:, S:]
     choice_lat = np.argmin(pred_ho[:, :S], axis=1)
     choice_thr = np.where(allowed, pred_ho[:, S:], np.inf).argmin(axis=1)
     g.set_policy(g.POLICY_FIXED)
     heur = np.array([g.choose_schedule(int(m), int(k), int(nn), batch=True) for m, k, nn in d["heldout_dims"]])
+    choice_rule = margin_rule(pred_ho[:, S:], choice_thr, heur)
     thr_allowed = np.where(allowed[None, :], thr_ho, -1.0)
     report = {
         "train_shapes": int(n), "validation_shapes": int(val.sum()), "heldout_shapes": int(len(Xho)),
@@ -198,6 +226,8 @@ def main():
         "regret_batch_fixed_heuristic": summarize(regret(thr_allowed, heur)),
         "time_weighted_regret_batch_model": time_weighted(thr_allowed, choice_thr),
         "time_weighted_regret_batch_fixed_heuristic": time_weighted(thr_allowed, heur),
+        "regret_batch_library_rule": summarize(regret(thr_allowed, choice_rule)),
+        "time_weighted_regret_batch_library_rule": time_weighted(thr_allowed, choice_rule),
     }
     np.savez(args.out, params=params, norm=norm, target_mean=tmean, target_std=tstd,
              history=np.array(history), report=json.dumps(report))

@@ -212,6 +212,21 @@ def test_resolve_schedule_without_gpu():
             raise AssertionError(f"{bad} accepted")
 
 
+def test_autotune_candidates_validation():
+    """The partial re-timing call refuses an out-of-range candidate index, a negative count, a
+    missing list and a bad density with GF2_ERR_INVALID_ARG before any device work."""
+    import ctypes
+    import paper_0811_1714_amd as g
+    S = g.num_candidates()
+    for cands, dens in (([S], 0.5), ([-1], 0.5), ([0, S + 3], 0.5), ([1], 1.5), ([1], -0.1)):
+        with pytest.raises(g.GF2Error) as ei:
+            g.autotune_candidates(100, 100, 100, cands, density=dens)
+        assert ei.value.status == 1, (cands, dens)
+    ms = (ctypes.c_float * S)()
+    assert g.lib().gf2_autotune_candidates(100, 100, 100, 0.5, 1, 1, None, 1, ms, None) == 1
+    assert g.lib().gf2_autotune_candidates(100, 100, 100, 0.5, 1, 1, None, -1, ms, None) == 1
+
+
 def test_autotune_cache_failure_paths(tmp_path):
     """Corrupt, truncated and missing autotune cache files are refused with GF2_ERR_INVALID_ARG and
     leave the cache as it was; a well-formed file loads, and saving it back gives the same entries."""

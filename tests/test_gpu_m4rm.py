@@ -182,7 +182,7 @@ def test_wide_strides_use_the_fallback_tiles(g):
     """Rows of 2^20 words or more overflow the 32-bit offsets some tiles use: the four-table
     tiles hand such an A to the 1408-row two-table tile, the one-word tiles hand such a B to
     the eight-table tile.  The bits must not change."""
-    for v in (16, 17, 18):
+    for v in (16, 17, 18, 22):
         print(f"lda >= 2^20, variant {v}", flush=True)
         run_and_check(g, 3, 100, 700, schedule=M4RM(v), seed=41, lda_pad=1 << 20)
     for v in (14, 15):

@@ -84,6 +84,12 @@ def test_autotune_and_policies_keep_bits(g):
     assert ms[best] == ms[ms > 0].min()
     mb, bb, copies = g.autotune_batch(300, 500, 700, density=0.5, reps=2)
     assert copies >= 2 and 0 <= bb < mb.size and mb[bb] > 0 and (mb > 0).sum() >= 7
+    # Partial re-timing: only the listed candidates get a time, alone or inside a batch.
+    sub = [7, 0, 28]
+    for batch in (False, True):
+        ps, pc = g.autotune_candidates(300, 500, 700, sub, density=0.5, reps=2, batch=batch)
+        assert (ps[sub] > 0).all() and (np.delete(ps, sub) == -1).all()
+        assert (pc >= 2) if batch else (pc == 1)
     try:
         base = run_and_check(g, 700, 900, 1100, seed=41)
         g.set_policy(g.POLICY_AUTOTUNE)

@@ -87,13 +87,15 @@ def test_committed_schedule_model_regret_recomputed():
     float64 forward pass of this module with the committed weights and feature normalisation,
     and the fixed heuristic's pick from the library (GF2_POLICY_FIXED, host code).  The model
     must be within 10% of the fastest candidate on average and strictly better on average than
-    the fixed heuristic; the training set must hold at least 12000 timed shapes."""
+    the fixed heuristic, both by its argmin and under the library's batch rule (the model's pick
+    only where predicted at least 10% faster than the fixed rule's); the training set must hold
+    at least 6000 timed shapes."""
     import os
     import paper_0811_1714_amd as g
     tune = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_0811_1714_amd", "tune")
     model = np.load(os.path.join(tune, "schedule_model.npz"))
     parts = [np.load(os.path.join(tune, f)) for f in sorted(os.listdir(tune)) if f.startswith("timings_mi355x_")]
-    assert sum(len(q["train_dims"]) for q in parts) >= 12000
+    assert sum(len(q["train_dims"]) for q in parts) >= 6000
     ho = [q for q in parts if len(q["heldout_dims"])]
     assert len(ho) == 1 and len(ho[0]["heldout_dims"]) == 500
     dims, dens, ms = ho[0]["heldout_dims"], ho[0]["heldout_density"], ho[0]["heldout_ms"].astype(np.float64)
@@ -118,8 +120,14 @@ def test_committed_schedule_model_regret_recomputed():
     finally:
         g.set_policy(pol)
     rows = np.arange(len(t))
+    # The library's batch rule: the model's pick replaces the fixed rule's only where its
+    # predicted time (the outputs are natural-log milliseconds) is at least 10% lower.
+    keep = Y[rows, S + pick_model] - Y[rows, S + pick_fixed] < np.log(0.9)
+    pick_rule = np.where(keep, pick_model, pick_fixed)
     r_model = t[rows, pick_model] / t.min(axis=1) - 1
+    r_rule = t[rows, pick_rule] / t.min(axis=1) - 1
     r_fixed = t[rows, pick_fixed] / t.min(axis=1) - 1
-    assert np.isfinite(r_model).all() and np.isfinite(r_fixed).all()
-    assert r_model.mean() <= 0.10
+    assert np.isfinite(r_model).all() and np.isfinite(r_fixed).all() and np.isfinite(r_rule).all()
+    assert r_model.mean() <= 0.10 and r_rule.mean() <= 0.10
     assert r_model.mean() < r_fixed.mean(), (r_model.mean(), r_fixed.mean())
+    assert r_rule.mean() < r_fixed.mean(), (r_rule.mean(), r_fixed.mean())
