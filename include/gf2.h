@@ -180,8 +180,12 @@ int32_t gf2_batch_plan_schedule(gf2_batch_plan plan, int64_t i);
  *                       batches use the tallest persistent-kernel tile by the same trade-off;
  *   GF2_POLICY_AUTOTUNE time every candidate once per shape bucket (powers of 2^(1/2)
  *                       of m, k, n), cache the fastest; falls back to FIXED under capture;
- *   GF2_POLICY_MODEL    the schedule model set by gf2_set_model (argmin of its predicted
- *                       log runtimes); falls back to FIXED when no model is set.
+ *   GF2_POLICY_MODEL    the schedule model set by gf2_set_model: a single product takes the
+ *                       argmin of its predicted log runtimes (latency head); a batch product
+ *                       takes the batch head's argmin only where it is predicted at least 10%
+ *                       faster than the FIXED candidate, else the FIXED candidate (the model's
+ *                       outputs are natural-log milliseconds); falls back to FIXED when no model
+ *                       is set.
  * Every schedule gives the same bits; the policy only changes the speed. */
 enum { GF2_POLICY_FIXED = 0, GF2_POLICY_AUTOTUNE = 1, GF2_POLICY_MODEL = 2 };
 gf2_status gf2_set_policy(int32_t policy);
