@@ -131,3 +131,49 @@ def test_committed_schedule_model_regret_recomputed():
     assert r_model.mean() <= 0.10 and r_rule.mean() <= 0.10
     assert r_model.mean() < r_fixed.mean(), (r_model.mean(), r_fixed.mean())
     assert r_rule.mean() < r_fixed.mean(), (r_rule.mean(), r_fixed.mean())
+
+
+def test_library_batch_rule_matches_its_definition():
+    """Under the model policy the library's batch pick (host inference, ``gf2_choose_schedule``)
+    is the batch head's argmin over the persistent-kernel candidates where that is predicted at
+    least 10% faster than the fixed rule's candidate, else the fixed rule's candidate.  Recomputed
+    here with the float64 forward pass on 300 fresh shapes; a disagreement is allowed only where
+    float32 and float64 could round differently (a near-tie in the argmin or at the margin)."""
+    import os
+    import paper_0811_1714_amd as g
+    if not os.path.exists(g.DEFAULT_MODEL):
+        pytest.skip("no trained model")
+    model = np.load(g.DEFAULT_MODEL)
+    S = g.num_candidates()
+    sizes = [4, 64, 64, 64, 2 * S]
+    flat, params, off = model["params"].astype(np.float64), [], 0
+    for fi, fo in zip(sizes[:-1], sizes[1:]):
+        params.append(flat[off: off + fi * fo].reshape(fi, fo)); off += fi * fo
+        params.append(flat[off: off + fo]); off += fo
+    norm = model["norm"].astype(np.float64)
+    rng = np.random.default_rng(2024)
+    dims = np.exp(rng.uniform(np.log(64), np.log(4096), (300, 3))).astype(np.int64)
+    X = (np.column_stack([np.log2(dims.astype(np.float64)), np.full(len(dims), 0.5)]) - norm[:4]) / norm[4:]
+    Y = mlp.forward(params, X)[0][:, S:]
+    allowed = np.array([g.batch_candidate(i) for i in range(S)])
+    pol = g.get_policy()
+    try:
+        g.set_policy(g.POLICY_FIXED)
+        fixed = np.array([g.choose_schedule(int(m), int(k), int(n), batch=True) for m, k, n in dims])
+        g.load_model()
+        g.set_policy(g.POLICY_MODEL)
+        lib_pick = np.array([g.choose_schedule(int(m), int(k), int(n), batch=True) for m, k, n in dims])
+    finally:
+        g.set_policy(pol)
+        g.set_model(None)
+    rows = np.arange(len(dims))
+    Ya = np.where(allowed[None, :], Y, np.inf)
+    arg = Ya.argmin(axis=1)
+    margin = Y[rows, arg] - Y[rows, fixed] - np.log(0.9)
+    want = np.where(margin < 0, arg, fixed)
+    second = np.sort(Ya, axis=1)[:, 1]
+    near = (np.abs(margin) < 1e-4) | (second - Ya[rows, arg] < 1e-4)
+    bad = (lib_pick != want) & ~near
+    assert not bad.any(), [(tuple(dims[i]), lib_pick[i], want[i]) for i in np.flatnonzero(bad)[:5]]
+    assert (want != fixed).sum() >= 10          # the rule does depart from the fixed heuristic
+    assert (want == fixed).sum() >= 10          # ... and does keep it
